@@ -1,0 +1,152 @@
+"""TEST INFRASTRUCTURE -- the CPU oracle of the complex MGS least-squares solver.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never calls it and shares no code with it.
+
+The oracle is a plain, sequential implementation, in its own double-double
+and quad-double arithmetic, of what the paper defines:
+
+* modified Gram-Schmidt QR (Section 3, Figure 1) on the matrix augmented with
+  the right-hand side (Section 3, Equation (1)),
+* column-oriented back substitution (Section 6, Figure 3),
+* least squares by sequential projections of b followed by back substitution,
+* the accuracy measure e of Section 4, Equation (2).
+
+Array layout ("planar"): a complex matrix with ``cols`` columns and leading
+dimension ``ld`` in L-limb precision is a float64 array of shape
+``(L, 2, cols, ld)``: ``X[l, 0]`` holds limb ``l`` of the real parts and
+``X[l, 1]`` limb ``l`` of the imaginary parts, column-major.  A vector is
+``(L, 2, len)``.  ``prec`` is the number of limbs: 1 (double), 2 (dd), 4 (qd).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liborc_mgs.so")
+_SRC = [os.path.join(_HERE, "orc_mgs.cpp"), os.path.join(_HERE, "orc_arith.hpp")]
+
+CXXFLAGS = ["-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-march=x86-64-v3",
+            "-fopenmp", "-fPIC", "-shared", "-Wall"]
+
+
+def build(force=True):
+    """Compile the oracle library in place with g++."""
+    if not force and os.path.exists(_SO):
+        return _SO
+    tmp = _SO + ".tmp%d" % os.getpid()
+    cmd = ["g++"] + CXXFLAGS + ["-o", tmp, _SRC[0]]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        L.orc_mgs.argtypes = [I, I, I, P, I, P, P, I, P, I, P, P, I]
+        L.orc_backsolve.argtypes = [I, I, P, I, P, P]
+        L.orc_ls_solve.argtypes = [I, I, I, P, I, P, I, P, P]
+        L.orc_arith.argtypes = [I, I, I, P, P, P]
+        L.orc_errors.argtypes = [I, I, I, P, I, P, I, P, I, P, I, P, I]
+        for f in (L.orc_mgs, L.orc_backsolve, L.orc_ls_solve, L.orc_arith, L.orc_errors):
+            f.restype = I
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def mgs(A, b=None, nthreads=0):
+    """MGS QR of A (planar (L,2,n,m)), augmented with b (planar (L,2,m)) if given.
+
+    Returns dict(Q, R, y, rho, info): Q (L,2,n,m), R (L,2,n,n) with zero lower
+    triangle, y (L,2,n) = Q^H b and rho (L,) = norm of the projected b
+    (the z of Equation (1)) when b is given.
+    """
+    A = _c(A)
+    L, two, n, m = A.shape
+    assert two == 2
+    Q = np.zeros_like(A)
+    R = np.zeros((L, 2, n, n))
+    y = rho = None
+    if b is not None:
+        b = _c(b)
+        assert b.shape == (L, 2, m)
+        y = np.zeros((L, 2, n))
+        rho = np.zeros(L)
+    info = lib().orc_mgs(L, m, n, _p(A), m, _p(b), _p(Q), m, _p(R), n, _p(y), _p(rho), int(nthreads))
+    if info < 0:
+        raise ValueError("orc_mgs argument error %d" % info)
+    return dict(Q=Q, R=R, y=y, rho=rho, info=info)
+
+
+def backsolve(R, y):
+    """Solve R x = y (Figure 3); R planar (L,2,n,n), y planar (L,2,n)."""
+    R = _c(R)
+    y = _c(y)
+    L, _, n, _ = R.shape
+    x = np.zeros((L, 2, n))
+    info = lib().orc_backsolve(L, n, _p(R), n, _p(y), _p(x))
+    if info < 0:
+        raise ValueError("orc_backsolve argument error %d" % info)
+    return x, info
+
+
+def ls_solve(Q, R, b):
+    """x = R^{-1} (Q^H b), Q^H b by sequential MGS projections of b."""
+    Q = _c(Q)
+    R = _c(R)
+    b = _c(b)
+    L, _, n, m = Q.shape
+    x = np.zeros((L, 2, n))
+    info = lib().orc_ls_solve(L, m, n, _p(Q), m, _p(R), n, _p(b), _p(x))
+    if info < 0:
+        raise ValueError("orc_ls_solve argument error %d" % info)
+    return x, info
+
+
+OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4}
+
+
+def arith(prec, op, a, b=None):
+    """Elementwise real dd/qd arithmetic: a, b of shape (count, prec) limbs."""
+    a = _c(a).reshape(-1, prec)
+    b = a if b is None else _c(b).reshape(-1, prec)
+    out = np.zeros_like(a)
+    rc = lib().orc_arith(prec, OPS[op], a.shape[0], _p(a), _p(b), _p(out))
+    if rc != 0:
+        raise ValueError("orc_arith error %d" % rc)
+    return out
+
+
+def errors(A, Q, R, cols=None, nthreads=0):
+    """(e_max of Equation (2), max_j ||a_j - Q r_j||/||a_j||, max |Q^H Q - I|).
+
+    Every difference is formed exactly (expansion arithmetic) and rounded once.
+    ``cols`` restricts the measures to the listed columns j.
+    """
+    A, Q, R = _c(A), _c(Q), _c(R)
+    L, _, n, m = A.shape
+    out = np.zeros(3)
+    cj = None if cols is None else np.ascontiguousarray(cols, dtype=np.int32)
+    lib().orc_errors(L, m, n, _p(A), m, _p(Q), m, _p(R), n, _p(cj), 0 if cj is None else len(cj),
+                     _p(out), int(nthreads))
+    return out

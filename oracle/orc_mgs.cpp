@@ -1,0 +1,356 @@
+// TEST INFRASTRUCTURE -- NOT PART OF THE PRODUCT PATH.
+//
+// CPU oracle for the complex modified Gram-Schmidt (MGS) least-squares
+// solver of Verschelde and Yoffe, "Orthogonalization on a General Purpose
+// Graphics Processing Unit with Double Double and Quad Double Arithmetic".
+// Plain, slow, sequential definitions written from the paper:
+//   * MGS, Section 3, Figure 1: for k = 1..n, r_kk = sqrt(a_k^H a_k),
+//     q_k = a_k / r_kk, then for j > k: r_kj = q_k^H a_j, a_j -= r_kj q_k.
+//   * Least squares, Section 3, Equation (1): MGS applied to [A b] yields
+//     R, y = Q^H b and the residual column; R x = y is then solved.
+//   * Back substitution, Section 6, Figure 3: column oriented, for k = n..1:
+//     x_k = y_k / r_kk, then y_j -= r_jk x_k for j < k.
+//   * The accuracy measure of Section 4, Equation (2).
+// Every reduction runs sequentially in ascending index order.  Only the loop
+// over independent trailing columns j is spread over OpenMP threads, so the
+// results are bitwise identical for every thread count.
+//
+// Storage ("planar"): a complex matrix of `cols` columns with leading
+// dimension ld is 2*L planes of ld*cols doubles; plane 2*l + part holds limb
+// l of the real (part 0) or imaginary (part 1) parts, column-major.
+#include "orc_arith.hpp"
+
+#include <omp.h>
+
+#include <cstdlib>
+#include <vector>
+
+using namespace orc;
+
+namespace {
+
+template <class T> using CV = std::vector<C<T>>;
+
+template <class T> void read_planar(const double *p, int rows, int cols, int ld, CV<T> &out) {
+  size_t plane = (size_t)ld * cols;
+  out.resize((size_t)rows * cols);
+  for (int j = 0; j < cols; ++j)
+    for (int i = 0; i < rows; ++i) out[(size_t)j * rows + i] = cload<T>(p, plane, (size_t)j * ld + i);
+}
+template <class T> void write_planar(double *p, int rows, int cols, int ld, const CV<T> &v) {
+  size_t plane = (size_t)ld * cols;
+  for (int j = 0; j < cols; ++j)
+    for (int i = 0; i < rows; ++i) cstore<T>(p, plane, (size_t)j * ld + i, v[(size_t)j * rows + i]);
+}
+
+template <class T> C<T> czero() { return {Limbs<T>::from(0.0), Limbs<T>::from(0.0)}; }
+
+// x^H y over rows [0, m), ascending.
+template <class T> C<T> inner(const C<T> *x, const C<T> *y, int m) {
+  C<T> s = czero<T>();
+  for (int i = 0; i < m; ++i) s = cadd(s, cmulc(x[i], y[i]));
+  return s;
+}
+
+// MGS on the columns of W (m x ncols, column-major, overwritten by Q in its
+// first n columns and by the projected remainder in columns n..ncols-1).
+// Columns 0..n-1 are normalised; any further columns are only projected
+// (the augmented right-hand side of Equation (1)).  R is n x ncols.
+template <class T> int mgs(int m, int n, int ncols, CV<T> &W, CV<T> &R, int nthreads) {
+  R.assign((size_t)n * ncols, czero<T>());
+  for (int k = 0; k < n; ++k) {
+    C<T> *ak = &W[(size_t)k * m];
+    T s = Limbs<T>::from(0.0);
+    for (int i = 0; i < m; ++i) s = add(s, cabs2(ak[i]));
+    if (is_zero(s) || !is_finite(s)) return k + 1;
+    T rkk = sqrt_(s);
+    for (int i = 0; i < m; ++i) ak[i] = cdivr(ak[i], rkk);
+    R[(size_t)k * n + k] = {rkk, Limbs<T>::from(0.0)};
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+    for (int j = k + 1; j < ncols; ++j) {
+      C<T> *aj = &W[(size_t)j * m];
+      C<T> r = inner(ak, aj, m);
+      R[(size_t)j * n + k] = r;
+      for (int i = 0; i < m; ++i) aj[i] = csub(aj[i], cmul(r, ak[i]));
+    }
+  }
+  return 0;
+}
+
+// Figure 3, column oriented.  R is n x n with leading dimension ldr.
+template <class T> void backsolve(int n, const C<T> *R, int ldr, CV<T> y, C<T> *x) {
+  for (int k = n - 1; k >= 0; --k) {
+    x[k] = cdivr(y[k], R[(size_t)k * ldr + k].re);
+    for (int j = 0; j < k; ++j) y[j] = csub(y[j], cmul(R[(size_t)k * ldr + j], x[k]));
+  }
+}
+
+template <class T>
+int run_mgs(int m, int n, const double *A, int lda, const double *b, double *Q, int ldq, double *R,
+            int ldr, double *y, double *rho, int nthreads) {
+  int ncols = n + (b ? 1 : 0);
+  CV<T> W;
+  read_planar<T>(A, m, n, lda, W);
+  if (b) {
+    CV<T> bb;
+    read_planar<T>(b, m, 1, m, bb);
+    W.insert(W.end(), bb.begin(), bb.end());
+  }
+  CV<T> Rv;
+  int info = mgs<T>(m, n, ncols, W, Rv, nthreads);
+  // Q: the first n columns of W.
+  CV<T> Qv(W.begin(), W.begin() + (size_t)m * n);
+  write_planar<T>(Q, m, n, ldq, Qv);
+  CV<T> Rn((size_t)n * n);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) Rn[(size_t)j * n + i] = Rv[(size_t)j * n + i];
+  write_planar<T>(R, n, n, ldr, Rn);
+  if (b) {
+    CV<T> yv(Rv.begin() + (size_t)n * n, Rv.begin() + (size_t)n * n + n);
+    if (y) write_planar<T>(y, n, 1, n, yv);
+    if (rho) {
+      // Norm of the projected right-hand side: z of Equation (1).
+      T s = Limbs<T>::from(0.0);
+      const C<T> *res = &W[(size_t)n * m];
+      for (int i = 0; i < m; ++i) s = add(s, cabs2(res[i]));
+      T z = sqrt_(s);
+      const double *zp = reinterpret_cast<const double *>(&z);
+      for (int l = 0; l < Limbs<T>::L; ++l) rho[l] = zp[l];
+    }
+  }
+  return info;
+}
+
+template <class T>
+int run_backsolve(int n, const double *R, int ldr, const double *y, double *x) {
+  CV<T> Rv, yv;
+  read_planar<T>(R, n, n, ldr, Rv);
+  read_planar<T>(y, n, 1, n, yv);
+  for (int k = 0; k < n; ++k)
+    if (is_zero(Rv[(size_t)k * n + k].re) || !is_finite(Rv[(size_t)k * n + k].re)) return k + 1;
+  CV<T> xv((size_t)n);
+  backsolve<T>(n, Rv.data(), n, yv, xv.data());
+  write_planar<T>(x, n, 1, n, xv);
+  return 0;
+}
+
+// Section 3: y = Q^H b by sequential MGS projections of b (the same
+// operations as the augmented column of Equation (1)), then Figure 3.
+template <class T>
+int run_ls_solve(int m, int n, const double *Q, int ldq, const double *R, int ldr, const double *b,
+                 double *x) {
+  CV<T> Qv, Rv, bv;
+  read_planar<T>(Q, m, n, ldq, Qv);
+  read_planar<T>(R, n, n, ldr, Rv);
+  read_planar<T>(b, m, 1, m, bv);
+  CV<T> yv((size_t)n);
+  for (int k = 0; k < n; ++k) {
+    const C<T> *qk = &Qv[(size_t)k * m];
+    C<T> r = inner(qk, bv.data(), m);
+    yv[k] = r;
+    for (int i = 0; i < m; ++i) bv[i] = csub(bv[i], cmul(r, qk[i]));
+  }
+  for (int k = 0; k < n; ++k)
+    if (is_zero(Rv[(size_t)k * n + k].re) || !is_finite(Rv[(size_t)k * n + k].re)) return k + 1;
+  CV<T> xv((size_t)n);
+  backsolve<T>(n, Rv.data(), n, yv, xv.data());
+  write_planar<T>(x, n, 1, n, xv);
+  return 0;
+}
+
+// Elementwise real arithmetic probes: a, b, out hold `count` numbers of L
+// limbs each, limbs of one number contiguous.
+template <class T> int run_arith(int op, int count, const double *a, const double *b, double *out) {
+  const int L = Limbs<T>::L;
+  for (int i = 0; i < count; ++i) {
+    T x, y, z;
+    double *xp = reinterpret_cast<double *>(&x), *yp = reinterpret_cast<double *>(&y);
+    for (int l = 0; l < L; ++l) {
+      xp[l] = a[(size_t)i * L + l];
+      yp[l] = b[(size_t)i * L + l];
+    }
+    switch (op) {
+      case 0: z = add(x, y); break;
+      case 1: z = sub(x, y); break;
+      case 2: z = mul(x, y); break;
+      case 3: z = div_(x, y); break;
+      case 4: z = sqrt_(x); break;
+      default: return -3;
+    }
+    double *zp = reinterpret_cast<double *>(&z);
+    for (int l = 0; l < L; ++l) out[(size_t)i * L + l] = zp[l];
+  }
+  return 0;
+}
+
+// e := e + sign * a * b exactly, a and b given as L-limb arrays.
+static inline int exp_add_prod_l(double *e, int n, const double *a, const double *b, int L, double sign) {
+  for (int i = 0; i < L; ++i) {
+    if (a[i] == 0.0) continue;
+    for (int j = 0; j < L; ++j) {
+      if (b[j] == 0.0) continue;
+      double p, err;
+      two_prod(sign * a[i], b[j], p, err);
+      n = exp_grow(e, n, p, e);
+      if (err != 0.0) n = exp_grow(e, n, err, e);
+    }
+  }
+  return n;
+}
+static inline int exp_add_limbs(double *e, int n, const double *a, int L, double sign) {
+  for (int i = 0; i < L; ++i)
+    if (a[i] != 0.0) n = exp_grow(e, n, sign * a[i], e);
+  return n;
+}
+static inline double exp_value(const double *e, int n) {
+  double scr[4096];
+  return n > 0 ? exp_approx(e, n, scr) : 0.0;
+}
+
+// Accuracy measures, every difference formed EXACTLY as an expansion and
+// only its final value rounded to FP64:
+//   out[0] = e_max of Equation (2): max_ij |a_ij - sum_l q_il r_lj|,
+//   out[1] = max_j ||a_j - Q r_j||_2 / ||a_j||_2,
+//   out[2] = max_lj |(Q^H Q - I)_lj|.
+// Columns j are those listed in `cols` (all when cols == NULL).
+template <class T>
+void run_errors(int m, int n, const double *A, int lda, const double *Q, int ldq, const double *R,
+                int ldr, const int *cols, int ncols, double *out, int nthreads) {
+  const int L = Limbs<T>::L;
+  CV<T> Av, Qv, Rv;
+  read_planar<T>(A, m, n, lda, Av);
+  read_planar<T>(Q, m, n, ldq, Qv);
+  read_planar<T>(R, n, n, ldr, Rv);
+  std::vector<int> js;
+  if (cols)
+    js.assign(cols, cols + ncols);
+  else
+    for (int j = 0; j < n; ++j) js.push_back(j);
+  int nj = (int)js.size();
+  std::vector<double> emax(nj, 0.0), bw(nj, 0.0), orth(nj, 0.0);
+#pragma omp parallel for schedule(dynamic) num_threads(nthreads)
+  for (int t = 0; t < nj; ++t) {
+    int j = js[t];
+    std::vector<double> er(4096), ei(4096);
+    double e = 0.0, s2 = 0.0, a2 = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const C<T> &a = Av[(size_t)j * m + i];
+      const double *ar = reinterpret_cast<const double *>(&a.re), *ai = reinterpret_cast<const double *>(&a.im);
+      int nr = exp_add_limbs(er.data(), 0, ar, L, 1.0);
+      int ni = exp_add_limbs(ei.data(), 0, ai, L, 1.0);
+      for (int l = 0; l <= j; ++l) {
+        const C<T> &q = Qv[(size_t)l * m + i];
+        const C<T> &r = Rv[(size_t)j * n + l];
+        const double *qr = reinterpret_cast<const double *>(&q.re), *qi = reinterpret_cast<const double *>(&q.im);
+        const double *rr = reinterpret_cast<const double *>(&r.re), *ri = reinterpret_cast<const double *>(&r.im);
+        nr = exp_add_prod_l(er.data(), nr, qr, rr, L, -1.0);
+        nr = exp_add_prod_l(er.data(), nr, qi, ri, L, 1.0);
+        ni = exp_add_prod_l(ei.data(), ni, qr, ri, L, -1.0);
+        ni = exp_add_prod_l(ei.data(), ni, qi, rr, L, -1.0);
+      }
+      double dr = exp_value(er.data(), nr), di = exp_value(ei.data(), ni);
+      double d = std::hypot(dr, di);
+      if (d > e) e = d;
+      s2 += dr * dr + di * di;
+      a2 += hi(a.re) * hi(a.re) + hi(a.im) * hi(a.im);
+    }
+    emax[t] = e;
+    bw[t] = (a2 > 0) ? std::sqrt(s2 / a2) : 0.0;
+    double o = 0.0;
+    for (int l = 0; l < n; ++l) {
+      int nr = 0, ni = 0;
+      if (l == j) { double one = 1.0; nr = exp_add_limbs(er.data(), 0, &one, 1, -1.0); }
+      for (int i = 0; i < m; ++i) {
+        const C<T> &x = Qv[(size_t)l * m + i];
+        const C<T> &y = Qv[(size_t)j * m + i];
+        const double *xr = reinterpret_cast<const double *>(&x.re), *xi = reinterpret_cast<const double *>(&x.im);
+        const double *yr = reinterpret_cast<const double *>(&y.re), *yi = reinterpret_cast<const double *>(&y.im);
+        // conj(x) * y = (xr yr + xi yi) + i (xr yi - xi yr)
+        nr = exp_add_prod_l(er.data(), nr, xr, yr, L, 1.0);
+        nr = exp_add_prod_l(er.data(), nr, xi, yi, L, 1.0);
+        ni = exp_add_prod_l(ei.data(), ni, xr, yi, L, 1.0);
+        ni = exp_add_prod_l(ei.data(), ni, xi, yr, L, -1.0);
+      }
+      double v = std::hypot(exp_value(er.data(), nr), exp_value(ei.data(), ni));
+      if (v > o) o = v;
+    }
+    orth[t] = o;
+  }
+  out[0] = out[1] = out[2] = 0.0;
+  for (int t = 0; t < nj; ++t) {
+    if (emax[t] > out[0]) out[0] = emax[t];
+    if (bw[t] > out[1]) out[1] = bw[t];
+    if (orth[t] > out[2]) out[2] = orth[t];
+  }
+}
+
+int threads_or_default(int t) { return t > 0 ? t : omp_get_max_threads(); }
+
+}  // namespace
+
+extern "C" {
+
+// prec: limbs per real number, 1 (double), 2 (dd) or 4 (qd).
+// A: m x n planar, lda >= m.  b: m planar (ld m) or NULL.
+// Q: m x n planar (ldq).  R: n x n planar (ldr >= n), lower triangle zero.
+// y: n planar (written when b != NULL).  rho: L limbs of the norm z of the
+// projected right-hand side (when b != NULL).  Returns 0, k>0 when column k
+// had a zero or non-finite norm, or <0 for bad arguments.
+int orc_mgs(int prec, int m, int n, const double *A, int lda, const double *b, double *Q, int ldq,
+            double *R, int ldr, double *y, double *rho, int nthreads) {
+  if (n < 1 || m < n || lda < m || ldq < m || ldr < n) return -1;
+  if (!A || !Q || !R) return -2;
+  int t = threads_or_default(nthreads);
+  switch (prec) {
+    case 1: return run_mgs<double>(m, n, A, lda, b, Q, ldq, R, ldr, y, rho, t);
+    case 2: return run_mgs<DD>(m, n, A, lda, b, Q, ldq, R, ldr, y, rho, t);
+    case 4: return run_mgs<QD>(m, n, A, lda, b, Q, ldq, R, ldr, y, rho, t);
+  }
+  return -3;
+}
+
+int orc_backsolve(int prec, int n, const double *R, int ldr, const double *y, double *x) {
+  if (n < 1 || ldr < n) return -1;
+  switch (prec) {
+    case 1: return run_backsolve<double>(n, R, ldr, y, x);
+    case 2: return run_backsolve<DD>(n, R, ldr, y, x);
+    case 4: return run_backsolve<QD>(n, R, ldr, y, x);
+  }
+  return -3;
+}
+
+int orc_ls_solve(int prec, int m, int n, const double *Q, int ldq, const double *R, int ldr,
+                 const double *b, double *x) {
+  if (n < 1 || m < n || ldq < m || ldr < n) return -1;
+  switch (prec) {
+    case 1: return run_ls_solve<double>(m, n, Q, ldq, R, ldr, b, x);
+    case 2: return run_ls_solve<DD>(m, n, Q, ldq, R, ldr, b, x);
+    case 4: return run_ls_solve<QD>(m, n, Q, ldq, R, ldr, b, x);
+  }
+  return -3;
+}
+
+// op: 0 add, 1 sub, 2 mul, 3 div, 4 sqrt (of a).
+int orc_arith(int prec, int op, int count, const double *a, const double *b, double *out) {
+  switch (prec) {
+    case 1: return run_arith<double>(op, count, a, b, out);
+    case 2: return run_arith<DD>(op, count, a, b, out);
+    case 4: return run_arith<QD>(op, count, a, b, out);
+  }
+  return -3;
+}
+
+// out[0] = e_max of Equation (2); out[1] = max_j ||a_j - Q r_j|| / ||a_j||;
+// out[2] = max |(Q^H Q - I)_lj|; over the columns j in cols[0..ncols) or all.
+int orc_errors(int prec, int m, int n, const double *A, int lda, const double *Q, int ldq,
+               const double *R, int ldr, const int *cols, int ncols, double *out, int nthreads) {
+  int t = threads_or_default(nthreads);
+  switch (prec) {
+    case 1: run_errors<double>(m, n, A, lda, Q, ldq, R, ldr, cols, ncols, out, t); return 0;
+    case 2: run_errors<DD>(m, n, A, lda, Q, ldq, R, ldr, cols, ncols, out, t); return 0;
+    case 4: run_errors<QD>(m, n, A, lda, Q, ldq, R, ldr, cols, ncols, out, t); return 0;
+  }
+  return -3;
+}
+
+}  // extern "C"

@@ -1,0 +1,255 @@
+"""Seeded synthetic inputs for the complex MGS least-squares solver.
+
+This module only draws random numbers and assembles inputs; it holds none of
+the solver's arithmetic and is the one piece shared by the HIP path's tests
+and benchmark and by the CPU oracle's tests.
+
+Every array is "planar" float64: a complex matrix of n columns and m rows in
+L-limb precision has shape (L, 2, n, m) (limb, real/imag, column, row); a
+vector has shape (L, 2, m).  Limbs are normalised, |x_{k+1}| <= ulp(x_k)/2.
+
+Seeds: ``numpy.random.default_rng([12100800, config, system, role])`` with
+roles 0 = A, 1 = x_true, 2 = b or noise, 3 = g (adjoint seed), 4 = sampled
+entries.
+
+Workloads (the paper draws random complex matrices, Section 8; the Jacobian
+of a polynomial system of degree d holds values of modulus 10^(+-d),
+Section 4):
+
+* ``config1`` -- dd, 32 x 32, re/im hi limbs U[-1,1], lo = hi 2^-53 U[-1,1];
+  x_true alike; b = A x_true rounded to dd from the exact sum.
+* ``config2`` -- qd, 320 x 256, limb k = hi 2^(-53k) U_k[-1,1]; b = A x_true
+  + noise of modulus 1e-40, rounded to qd from the exact sum.
+* ``config3`` -- dd, 1024 x 1024 systems (64 back to back): re, im ~ N(0,1),
+  column j scaled by fl(10^s_j), s_j ~ U[-12,12]; each entry is the exact
+  dd product of the scale and the Gaussian; x_true complex N(0,1);
+  b = A x_true to dd accuracy.
+* ``config5`` -- dd, 512 x 384, A, b, g with N(0,1) hi limbs.
+* ``table2_matrix`` -- 32 x 32 entries r e^{i theta}, theta ~ U[0, 2 pi),
+  log10 r ~ U[-g, g] (Section 4, Table 2).
+"""
+import numpy as np
+
+SEED0 = 12100800
+
+
+def rng(config, system=0, role=0):
+    return np.random.default_rng([SEED0, int(config), int(system), int(role)])
+
+
+# ----------------------------------------------------------- limb assembly --
+def _two_sum(a, b):
+    s = a + b
+    bb = s - a
+    return s, (a - (s - bb)) + (b - bb)
+
+
+def normalize(limbs):
+    """Exactly re-express sum(limbs) as normalised limbs (same count).
+
+    Repeated TwoSum distillation; every step is error free, so the value is
+    unchanged.  Verifies |x_{k+1}| <= ulp(x_k)/2 on return.
+    """
+    x = [np.array(v, dtype=np.float64, copy=True) for v in limbs]
+    L = len(x)
+    out = []
+    rest = x
+    for _ in range(L):
+        for _ in range(4):
+            for i in range(len(rest) - 1, 0, -1):
+                rest[i - 1], rest[i] = _two_sum(rest[i - 1], rest[i])
+        out.append(rest[0])
+        rest = rest[1:]
+    for _ in range(8):
+        ok = True
+        for k in range(L - 1):
+            s, e = _two_sum(out[k], out[k + 1])
+            out[k], out[k + 1] = s, e
+        for k in range(L - 1):
+            if np.any(np.abs(out[k + 1]) > 0.5 * np.spacing(np.abs(out[k]))):
+                ok = False
+        if ok:
+            break
+    else:
+        raise RuntimeError("limb normalisation did not converge")
+    return out
+
+
+def random_limbs(g, shape, L, dist="uniform"):
+    """Random L-limb reals: hi from `dist`, limb k = hi 2^(-53k) U_k[-1,1]."""
+    if dist == "uniform":
+        hi = g.uniform(-1.0, 1.0, shape)
+    elif dist == "normal":
+        hi = g.standard_normal(shape)
+    else:
+        raise ValueError(dist)
+    limbs = [hi] + [hi * 2.0 ** (-53 * k) * g.uniform(-1.0, 1.0, shape) for k in range(1, L)]
+    return np.stack(normalize(limbs)) if L > 1 else hi[None]
+
+
+def random_complex(g, shape, L, dist="uniform"):
+    """Planar (L, 2, *shape) complex numbers, real then imaginary draws."""
+    re = random_limbs(g, shape, L, dist)
+    im = random_limbs(g, shape, L, dist)
+    return np.ascontiguousarray(np.stack([re, im], axis=1))
+
+
+# ------------------------------------------------- exact right-hand sides --
+def _to_int(v, S):
+    """Exact integer v * 2^S for a float64 array v (|v| >= 2^-S)."""
+    out = []
+    for f in np.asarray(v, dtype=np.float64).ravel().tolist():
+        num, den = f.as_integer_ratio()
+        out.append(num << (S - den.bit_length() + 1))
+    return out
+
+
+def _round_int(t, S, L):
+    """Round the exact value t / 2^S to L normalised float64 limbs."""
+    limbs = []
+    for _ in range(L):
+        f = t / (1 << S) if t != 0 else 0.0  # int / int is correctly rounded
+        limbs.append(f)
+        if f != 0.0:
+            num, den = f.as_integer_ratio()
+            t -= num << (S - den.bit_length() + 1)
+    return limbs
+
+
+def exact_matvec(A, x, L_out, extra=None):
+    """Round-to-L_out-limbs of the exact product A x (+ extra), Python integers.
+
+    For small problems only (m n of a few 10^5).
+    """
+    La, _, n, m = A.shape
+    S = 1200
+    Ar = [sum(col) for col in zip(*[_to_int(A[l, 0], S) for l in range(La)])]
+    Ai = [sum(col) for col in zip(*[_to_int(A[l, 1], S) for l in range(La)])]
+    Lx = x.shape[0]
+    xr = [sum(c) for c in zip(*[_to_int(x[l, 0], S) for l in range(Lx)])]
+    xi = [sum(c) for c in zip(*[_to_int(x[l, 1], S) for l in range(Lx)])]
+    if extra is not None:
+        Le = extra.shape[0]
+        er = [sum(c) << S for c in zip(*[_to_int(extra[l, 0], S) for l in range(Le)])]
+        ei = [sum(c) << S for c in zip(*[_to_int(extra[l, 1], S) for l in range(Le)])]
+    else:
+        er = [0] * m
+        ei = [0] * m
+    b = np.zeros((L_out, 2, m))
+    for i in range(m):
+        sr, si = er[i], ei[i]
+        for j in range(n):
+            a_r, a_i = Ar[j * m + i], Ai[j * m + i]
+            sr += a_r * xr[j] - a_i * xi[j]
+            si += a_r * xi[j] + a_i * xr[j]
+        b[:, 0, i] = _round_int(sr, 2 * S, L_out)
+        b[:, 1, i] = _round_int(si, 2 * S, L_out)
+    return b
+
+
+def _split(a):
+    c = 134217729.0 * a
+    h = c - (c - a)
+    return h, a - h
+
+
+def _two_prod(a, b):
+    p = a * b
+    ah, al = _split(a)
+    bh, bl = _split(b)
+    return p, ((ah * bh - p) + ah * bl + al * bh) + al * bl
+
+
+def dd_matvec_dx(A, x):
+    """b = A x for dd A (2,2,n,m) and FP64 x (1,2,n), to dd accuracy.
+
+    Exact leading products and sums (TwoProd, TwoSum) with the rounding
+    errors and the low-limb products gathered in one FP64 accumulator per
+    component, then renormalised (compensated dot product).
+    """
+    _, _, n, m = A.shape
+    xr, xi = x[0, 0], x[0, 1]
+    S = [np.zeros(m), np.zeros(m)]
+    Cc = [np.zeros(m), np.zeros(m)]
+    for j in range(n):
+        ahr, ahi, alr, ali = A[0, 0, j], A[0, 1, j], A[1, 0, j], A[1, 1, j]
+        # real: ar xr - ai xi ; imag: ar xi + ai xr
+        for comp, terms in ((0, ((ahr, alr, xr[j], 1.0), (ahi, ali, xi[j], -1.0))),
+                            (1, ((ahr, alr, xi[j], 1.0), (ahi, ali, xr[j], 1.0)))):
+            for h, lo, xv, sg in terms:
+                p, e = _two_prod(h, sg * xv)
+                S[comp], t = _two_sum(S[comp], p)
+                Cc[comp] = Cc[comp] + (e + t + lo * (sg * xv))
+    b = np.zeros((2, 2, m))
+    for comp in range(2):
+        s, e = _two_sum(S[comp], Cc[comp])
+        b[0, comp], b[1, comp] = s, e
+    return b
+
+
+# ----------------------------------------------------------------- configs --
+def config1():
+    """dd 32 x 32 (configuration 1). Returns dict(A, b, x_true, prec)."""
+    m = n = 32
+    A = random_complex(rng(1, 0, 0), (n, m), 2)
+    x = random_complex(rng(1, 0, 1), (n,), 2)
+    b = exact_matvec(A, x, 2)
+    return dict(A=A, b=b, x_true=x, prec=2, m=m, n=n)
+
+
+def config2():
+    """qd 320 x 256 overdetermined with 1e-40 noise (configuration 2)."""
+    m, n = 320, 256
+    A = random_complex(rng(2, 0, 0), (n, m), 4)
+    x = random_complex(rng(2, 0, 1), (n,), 4)
+    noise = random_complex(rng(2, 0, 2), (m,), 4) * 1e-40
+    noise = np.stack([np.stack(normalize(list(noise[:, p]))) for p in range(2)], axis=1)
+    b = exact_matvec(A, x, 4, extra=noise)
+    return dict(A=A, b=b, x_true=x, prec=4, m=m, n=n)
+
+
+def config3(system=0, m=1024, n=1024):
+    """One dd Jacobian-like system with column scales 10^s, s ~ U[-12,12]."""
+    g = rng(3, system, 0)
+    G = g.standard_normal((2, n, m))
+    s = g.uniform(-12.0, 12.0, n)
+    c = 10.0 ** s
+    A = np.zeros((2, 2, n, m))
+    for p in range(2):
+        h, lo = _two_prod(c[:, None], G[p])
+        A[0, p], A[1, p] = h, lo
+    A[:] = np.stack([np.stack(normalize([A[0, p], A[1, p]])) for p in range(2)], axis=1)
+    xg = rng(3, system, 1)
+    x = np.zeros((1, 2, n))
+    x[0] = xg.standard_normal((2, n))
+    b = dd_matvec_dx(A, x)
+    x2 = np.zeros((2, 2, n))
+    x2[0] = x[0]
+    return dict(A=np.ascontiguousarray(A), b=np.ascontiguousarray(b), x_true=x2, prec=2, m=m, n=n,
+                scales=c)
+
+
+def config5():
+    """dd 512 x 384 Gaussian A, b and adjoint seed g (configuration 5)."""
+    m, n = 512, 384
+    A = random_complex(rng(5, 0, 0), (n, m), 2, "normal")
+    b = random_complex(rng(5, 0, 2), (m,), 2, "normal")
+    gx = random_complex(rng(5, 0, 3), (n,), 2, "normal")
+    return dict(A=A, b=b, g=gx, prec=2, m=m, n=n)
+
+
+def random_problem(prec, m, n, seed=0, dist="uniform", config=0):
+    """Generic seeded test problem: A (prec,2,n,m) and b (prec,2,m)."""
+    A = random_complex(rng(config, seed, 0), (n, m), prec, dist)
+    b = random_complex(rng(config, seed, 2), (m,), prec, dist)
+    return dict(A=A, b=b, prec=prec, m=m, n=n)
+
+
+def table2_matrix(g_rng, g, L, m=32, n=32):
+    """Table 2 workload: entries r e^{i theta}, log10 r ~ U[-g, g] (FP64 values)."""
+    th = g_rng.uniform(0.0, 2.0 * np.pi, (n, m))
+    r = 10.0 ** g_rng.uniform(-g, g, (n, m))
+    A = np.zeros((L, 2, n, m))
+    A[0, 0] = r * np.cos(th)
+    A[0, 1] = r * np.sin(th)
+    return A

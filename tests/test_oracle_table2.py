@@ -1,0 +1,48 @@
+"""Statistical pin of the oracle against the accuracy table the paper prints.
+
+Section 4, Table 2 lists the range of log10(e), e the max-entry residual of
+Equation (2), over 1,000 random 32 x 32 complex QR decompositions whose
+entries r e^{i theta} have log10 r uniform in [-g, g] (the reading of "r
+chosen at random from [10^-g, 10^g]" under which the printed ranges are
+reproduced).  A dropped term, a wrong precision or a wrong scaling in the
+oracle's MGS shifts log10(e) by whole decades; a small sample must fall
+inside the printed range widened by half a decade, and its median inside
+the printed range widened by a quarter decade (the printed values are
+rounded to 0.1 and come from another implementation of dd/qd).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1210_0800_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "table2_accuracy.txt")
+LIMBS = {"d": 1, "dd": 2, "qd": 4}
+
+
+def _rows():
+    rows = []
+    for line in open(GOLD):
+        line = line.split("#")[0].split()
+        if line:
+            rows.append((int(line[0]), line[1], float(line[2]), float(line[3])))
+    return rows
+
+
+@pytest.mark.parametrize("g,prec,me,Me", _rows())
+def test_table2_ranges(g, prec, me, Me):
+    L = LIMBS[prec]
+    rng = inputs.rng(20, g, L)
+    nsamp = 6 if L == 4 else 12
+    logs = []
+    for _ in range(nsamp):
+        A = inputs.table2_matrix(rng, g, L)
+        o = oracle.mgs(A)
+        assert o["info"] == 0
+        e = oracle.errors(A, o["Q"], o["R"])[0]
+        logs.append(np.log10(e))
+    logs = np.array(logs)
+    assert logs.min() >= me - 0.5 and logs.max() <= Me + 0.5, (g, prec, logs)
+    assert me - 0.25 <= np.median(logs) <= Me + 0.25, (g, prec, np.median(logs))
