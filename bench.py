@@ -1,0 +1,186 @@
+"""Benchmark: complex double-double MGS least squares on MI355X.
+
+Workload (one "step"): 64 Jacobian-like complex dd systems of size
+1024 x 1024 (columns scaled by 10^s, s ~ U[-12, 12]) solved back to back on
+one stream, as the Newton corrections along one path: for each system, MGS
+on [A b] (mgs_qr) then back substitution (ls_backsolve).  Inputs are
+resident in HBM before the timed region.
+
+Prints one JSON line: solves/s, the roofline of the dominant kernel sequence
+(the MGS factorisation, FP64 vector ALU bound) and the CPU oracle baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "dd/qd MGS least-squares solves/s & %FP64 peak; refined vs plain at equal error"
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+
+# FP64 flops per operation of the dd kernels (FMA = 2), counted from the
+# formulations in paper_1210_0800_amd/csrc/ddqd.hpp.
+F_DD = dict(cmulc=60, upd=66, abs2=28, scale=20, merge=16)
+
+
+def mgs_flops(m, n, ncols, F=F_DD):
+    """Algorithmic FP64 flops of MGS on m x ncols (n normalised columns)."""
+    total = 0
+    for k in range(n):
+        rest = ncols - k - 1
+        total += m * F["abs2"] + (m - 1) * F["merge"] // 2 + m * F["scale"]
+        total += rest * (m * (F["cmulc"] + F["upd"]) + (m - 1) * F["merge"])
+    return total
+
+
+def backsolve_flops(n, F=F_DD):
+    return n * (n - 1) // 2 * F["upd"] + n * F["scale"]
+
+
+def _gen(i):
+    from paper_1210_0800_amd import inputs
+
+    d = inputs.config3(i)
+    return d["A"], d["b"]
+
+
+def make_inputs(nsys, workers):
+    if workers <= 1:
+        return [_gen(i) for i in range(nsys)]
+    import multiprocessing as mp
+
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_gen, range(nsys))
+
+
+def cpu_baseline(inputs_np, budget_s=20.0):
+    """Oracle (test infrastructure) timed on the host: whole dd 1024x1024 solves."""
+    import oracle
+
+    threads = len(os.sched_getaffinity(0))
+    done, t0 = 0, time.perf_counter()
+    for A, b in inputs_np:
+        o = oracle.mgs(A, b, nthreads=threads)
+        oracle.backsolve(o["R"], o["y"])
+        done += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="solves/s", cores=threads, kind="oracle",
+                sample="%d of the 64 dd 1024x1024 systems (MGS on [A b] + back substitution), %.1f s" %
+                (done, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--systems", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    m = n = 1024
+    t_gen = time.perf_counter()
+    workers = min(16, len(os.sched_getaffinity(0)))
+    host = make_inputs(args.systems, workers)
+    t_gen = time.perf_counter() - t_gen
+    print("bench: generated %d systems in %.1f s" % (args.systems, t_gen), file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_1210_0800_amd import api
+
+    dev = torch.device("cuda:0")
+    A = [torch.from_numpy(a).to(dev) for a, _ in host]
+    B = [torch.from_numpy(b).to(dev) for _, b in host]
+    Q = torch.empty_like(A[0])
+    R = torch.empty((2, 2, n, n), dtype=torch.float64, device=dev)
+    y = torch.empty((2, 2, n), dtype=torch.float64, device=dev)
+    rho = torch.empty(2, dtype=torch.float64, device=dev)
+    x = torch.empty((2, 2, n), dtype=torch.float64, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    info2 = torch.empty(1, dtype=torch.int32, device=dev)
+    work = api.workspace(m, n, 2, 0, dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def solve(i, ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        api.mgs_qr(A[i], B[i], Q=Q, R=R, y=y, rho=rho, info=info, work=work)
+        if ev is not None:
+            ev[1].record(stream)
+        api.ls_backsolve(R, y, x=x, info=info2)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        for i in range(args.systems):
+            solve(i)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0 and int(info2.item()) == 0
+
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
+              for _ in range(args.steps * args.systems)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        for i in range(args.systems):
+            solve(i, events[s * args.systems + i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print("bench: timed %d steps in %.3f s" % (args.steps, elapsed), file=sys.stderr, flush=True)
+
+    t_qr = np.mean([e[0].elapsed_time(e[1]) for e in events]) * 1e-3
+    t_bs = np.mean([e[1].elapsed_time(e[2]) for e in events]) * 1e-3
+    f_qr = mgs_flops(m, n, n + 1)
+    achieved = f_qr / t_qr / 1e12
+    solves = args.steps * args.systems
+    out = {
+        "metric": METRIC,
+        "value": solves / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "dd (2 x f64)",
+        "data": "synthetic",
+        "config": {
+            "workload": "complex double-double MGS least squares (MGS on [A b] + back substitution), "
+                        "A 1024x1024 Jacobian-like (N(0,1) entries, columns scaled by 10^U[-12,12]), "
+                        "64 systems solved back to back per step",
+            "m": m, "n": n, "systems_per_step": args.systems, "prec": "dd",
+            "ms_per_solve": elapsed / solves * 1e3,
+            "ms_mgs_qr": t_qr * 1e3, "ms_backsolve": t_bs * 1e3,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "mgs_step_kernel (all launches of one factorisation)",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": None,
+            "flops_per_solve": f_qr,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(host[:4])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,126 @@
+/*
+ * mgsqr -- complex least squares by modified Gram-Schmidt (MGS) in
+ * double-double (dd) and quad-double (qd) arithmetic on AMD MI355X (gfx950).
+ *
+ * Method: J. Verschelde and G. Yoffe, "Orthogonalization on a General
+ * Purpose Graphics Processing Unit with Double Double and Quad Double
+ * Arithmetic".  Section 3, Figure 1 defines MGS; Section 3, Equation (1)
+ * defines the least-squares solve by MGS on the matrix augmented with the
+ * right-hand side; Section 6, Figure 3 defines the column-oriented back
+ * substitution.
+ *
+ * ------------------------------------------------------------------------
+ * Number formats and layout ("planar", all device memory, float64):
+ *   prec = number of FP64 limbs per real number: 2 (dd) or 4 (qd).
+ *   A complex matrix with `cols` columns, leading dimension ld >= rows, is
+ *   2*prec planes of ld*cols doubles each; plane p = 2*limb + part holds
+ *   limb `limb` of the real (part 0) or imaginary (part 1) parts,
+ *   column-major: element (i, j) of plane p is at base[p*ld*cols + j*ld + i].
+ *   A vector of length len is the same with ld = len, cols = 1.
+ *   Inputs must be normalised: |x_{k+1}| <= ulp(x_k) / 2 limb by limb.
+ *   A PyTorch view of a matrix is a contiguous float64 tensor of shape
+ *   [prec, 2, cols, ld].
+ *
+ * Ownership: the caller allocates and frees every buffer, including the
+ * workspace, and keeps them alive until the work enqueued on `stream` has
+ * finished.  The library does not allocate, copy between host and device,
+ * or synchronise; it enqueues kernels on `stream` (NULL = default stream).
+ *
+ * Errors: the return value reports argument errors synchronously:
+ *   MGS_OK (0) success, MGS_ERR_DIMS, MGS_ERR_POINTER, MGS_ERR_PREC,
+ *   MGS_ERR_WORKSPACE, MGS_ERR_LAUNCH, MGS_ERR_UNSUPPORTED (negative).
+ * Numerical status goes to the device int *info (written by the kernels):
+ *   0 = success; k > 0 = column k (1-based) had a zero or non-finite norm
+ *   (MGS does not pivot, Section 4), outputs from column k on are then
+ *   unspecified.
+ * ------------------------------------------------------------------------
+ */
+#ifndef MGSQR_H
+#define MGSQR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+struct ihipStream_t; /* hipStream_t is `struct ihipStream_t *` */
+typedef struct ihipStream_t *mgs_stream_t;
+
+#define MGS_ABI_VERSION 1
+
+enum {
+  MGS_OK = 0,
+  MGS_ERR_DIMS = -1,        /* n < 1, m < n, ld too small, size above the supported maximum */
+  MGS_ERR_POINTER = -2,     /* required pointer NULL or not 8-byte aligned, forbidden aliasing */
+  MGS_ERR_PREC = -3,        /* prec not 2 or 4 */
+  MGS_ERR_WORKSPACE = -4,   /* work_bytes below mgs_workspace_size() */
+  MGS_ERR_LAUNCH = -5,      /* a kernel launch failed (HIP error) */
+  MGS_ERR_UNSUPPORTED = -6  /* unknown operation code */
+};
+
+enum { MGS_OP_QR = 0, MGS_OP_SOLVE = 1 };
+
+/* Largest supported row count m: dd 4096, qd 2048. */
+#define MGS_MAX_ROWS_DD 4096
+#define MGS_MAX_ROWS_QD 2048
+
+int mgs_abi_version(void);
+const char *mgs_status_string(int status);
+
+/* Bytes of device workspace needed by operation `op` (MGS_OP_QR with a
+ * right-hand side, MGS_OP_SOLVE) for an m x n problem; written to *bytes. */
+int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
+
+/*
+ * mgs_qr -- MGS QR of A (Section 3, Figure 1), optionally of [A b]
+ * (Section 3, Equation (1)).
+ *   A  [in]   m x n planar, lda >= m.  Not modified unless Q == A.
+ *   Q  [out]  m x n planar, ldq >= m; Q == A (with ldq == lda) overwrites A
+ *             in place as the paper's GPU algorithm does (Section 5).
+ *   R  [out]  n x n planar, ldr >= n: upper triangular with a real
+ *             positive diagonal (imaginary parts +0), lower triangle 0.
+ *   b  [in]   m planar or NULL.  When given, MGS runs on [A b]:
+ *   y  [out]  n planar, y = Q^H b as the projections of b (may be NULL
+ *             only when b is NULL).
+ *   rho[out]  prec doubles (the limbs of a real number) or NULL: the norm z
+ *             of the projected right-hand side, ||b - A x|| of the
+ *             least-squares solution x (Equation (1)).
+ *   work      workspace of mgs_workspace_size(m, n, prec, MGS_OP_QR) bytes
+ *             when b != NULL (may be NULL otherwise).
+ *   info      device int, see above.
+ * Requires 1 <= n <= m <= MGS_MAX_ROWS_{DD,QD}.
+ */
+int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq, double *R, int ldr,
+           const double *b, double *y, double *rho, void *work, size_t work_bytes, int *info,
+           mgs_stream_t stream);
+
+/*
+ * ls_solve -- least-squares solution x of A x = b from the MGS factors of
+ * A: y = Q^H b by n sequential MGS projections of b (the same operations as
+ * the augmented column of Equation (1)), then the back substitution of
+ * Section 6, Figure 3.
+ *   Q  [in] m x n planar (ldq), R [in] n x n planar (ldr), b [in] m planar,
+ *   x  [out] n planar.  work: mgs_workspace_size(m, n, prec, MGS_OP_SOLVE).
+ */
+int ls_solve(int m, int n, int prec, const double *Q, int ldq, const double *R, int ldr,
+             const double *b, double *x, void *work, size_t work_bytes, int *info,
+             mgs_stream_t stream);
+
+/*
+ * ls_backsolve -- x = R^{-1} y, column-oriented back substitution
+ * (Section 6, Figure 3): for k = n..1, x_k = y_k / r_kk, then
+ * y_j -= r_jk x_k for j < k.
+ *   R [in] n x n planar (ldr >= n), upper triangle and real diagonal read;
+ *   y [in] n planar (not modified); x [out] n planar.
+ *   info: 0, or k > 0 when r_kk is zero or not finite (smallest such k).
+ * Requires 1 <= n <= MGS_MAX_ROWS_{DD,QD}.
+ */
+int ls_backsolve(int n, int prec, const double *R, int ldr, const double *y, double *x, int *info,
+                 mgs_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGSQR_H */

@@ -1,0 +1,63 @@
+"""ctypes binding of libmgsqr.so (include/mgsqr.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of the library.  PyTorch supplies
+device memory and the stream.  Importing this module on a machine where the
+library was not built raises immediately: there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "libmgsqr.so")
+
+MGS_OK = 0
+MGS_OP_QR = 0
+MGS_OP_SOLVE = 1
+MGS_MAX_ROWS = {2: 4096, 4: 2048}
+
+EXPORTS = ("mgs_abi_version", "mgs_status_string", "mgs_workspace_size", "mgs_qr", "ls_solve",
+           "ls_backsolve")
+
+_lib = None
+
+
+class MgsError(RuntimeError):
+    def __init__(self, fn, status):
+        msg = lib().mgs_status_string(status).decode()
+        super().__init__("%s failed with status %d: %s" % (fn, status, msg))
+        self.status = status
+
+
+def lib():
+    """Load libmgsqr.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError("libmgsqr.so is not built (%s); run __graft_entry__.build()" % SO_PATH)
+        L = ctypes.CDLL(SO_PATH)
+        P, I, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+        L.mgs_abi_version.argtypes = []
+        L.mgs_abi_version.restype = I
+        L.mgs_status_string.argtypes = [I]
+        L.mgs_status_string.restype = ctypes.c_char_p
+        L.mgs_workspace_size.argtypes = [I, I, I, I, ctypes.POINTER(S)]
+        L.mgs_workspace_size.restype = I
+        L.mgs_qr.argtypes = [I, I, I, P, I, P, I, P, I, P, P, P, P, S, P, P]
+        L.mgs_qr.restype = I
+        L.ls_solve.argtypes = [I, I, I, P, I, P, I, P, P, P, S, P, P]
+        L.ls_solve.restype = I
+        L.ls_backsolve.argtypes = [I, I, P, I, P, P, P, P]
+        L.ls_backsolve.restype = I
+        _lib = L
+    return _lib
+
+
+def check(fn, status):
+    if status != MGS_OK:
+        raise MgsError(fn, status)
+
+
+def workspace_size(m, n, prec, op):
+    out = ctypes.c_size_t(0)
+    check("mgs_workspace_size", lib().mgs_workspace_size(m, n, prec, op, ctypes.byref(out)))
+    return out.value

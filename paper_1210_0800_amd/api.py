@@ -1,0 +1,103 @@
+"""Torch-facing wrappers of the C ABI (include/mgsqr.h).
+
+Tensors are float64, contiguous, on a HIP device, in the planar layout
+[prec, 2, cols, ld] (matrices) or [prec, 2, len] (vectors): limb, real /
+imaginary part, column, row.  prec = 2 (double-double) or 4 (quad-double).
+Work is enqueued on the current torch stream; nothing is synchronised.
+"""
+import torch
+
+from . import _lib
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(t):
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _check_planar(name, t, prec=None, ndim=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("%s must be a contiguous float64 tensor on a HIP device" % name)
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError("%s must have %d dimensions, got shape %s" % (name, ndim, tuple(t.shape)))
+    if t.shape[1] != 2 or (prec is not None and t.shape[0] != prec):
+        raise ValueError("%s must have shape [prec, 2, ...], got %s" % (name, tuple(t.shape)))
+
+
+def workspace(m, n, prec, op, device):
+    nbytes = _lib.workspace_size(m, n, prec, op)
+    return torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=device)
+
+
+def mgs_qr(A, b=None, *, Q=None, R=None, y=None, rho=None, info=None, work=None, with_rho=True):
+    """MGS QR of A (Figure 1), of [A b] when b is given (Equation (1)).
+
+    Returns dict(Q, R, y, rho, info) of device tensors; Q may be passed as A
+    itself to factor in place.
+    """
+    _check_planar("A", A, ndim=4)
+    prec, _, n, m = A.shape
+    dev = A.device
+    Q = torch.empty_like(A) if Q is None else Q
+    _check_planar("Q", Q, prec, 4)
+    if tuple(Q.shape) != tuple(A.shape):
+        raise ValueError("Q must have the shape of A")
+    R = torch.empty((prec, 2, n, n), dtype=torch.float64, device=dev) if R is None else R
+    _check_planar("R", R, prec, 4)
+    info = torch.empty(1, dtype=torch.int32, device=dev) if info is None else info
+    if b is not None:
+        _check_planar("b", b, prec, 3)
+        if b.shape[2] != m:
+            raise ValueError("b must have m = %d rows" % m)
+        y = torch.empty((prec, 2, n), dtype=torch.float64, device=dev) if y is None else y
+        if with_rho and rho is None:
+            rho = torch.empty(prec, dtype=torch.float64, device=dev)
+        work = workspace(m, n, prec, _lib.MGS_OP_QR, dev) if work is None else work
+    else:
+        y = rho = None
+    nwork = 0 if work is None else work.numel() * work.element_size()
+    st = _lib.lib().mgs_qr(m, n, prec, _ptr(A), m, _ptr(Q), m, _ptr(R), R.shape[3], _ptr(b), _ptr(y),
+                           _ptr(rho), _ptr(work), nwork, _ptr(info), _stream(A))
+    _lib.check("mgs_qr", st)
+    return dict(Q=Q, R=R, y=y, rho=rho, info=info)
+
+
+def ls_backsolve(R, y, *, x=None, info=None):
+    """x = R^-1 y by the column-oriented back substitution of Figure 3."""
+    _check_planar("R", R, ndim=4)
+    prec, _, n, ldr = R.shape
+    _check_planar("y", y, prec, 3)
+    x = torch.empty_like(y) if x is None else x
+    info = torch.empty(1, dtype=torch.int32, device=R.device) if info is None else info
+    st = _lib.lib().ls_backsolve(n, prec, _ptr(R), ldr, _ptr(y), _ptr(x), _ptr(info), _stream(R))
+    _lib.check("ls_backsolve", st)
+    return x, info
+
+
+def ls_solve(Q, R, b, *, x=None, info=None, work=None):
+    """x = R^-1 (Q^H b), Q^H b by sequential MGS projections of b."""
+    _check_planar("Q", Q, ndim=4)
+    prec, _, n, m = Q.shape
+    _check_planar("R", R, prec, 4)
+    _check_planar("b", b, prec, 3)
+    x = torch.empty((prec, 2, n), dtype=torch.float64, device=Q.device) if x is None else x
+    info = torch.empty(1, dtype=torch.int32, device=Q.device) if info is None else info
+    work = workspace(m, n, prec, _lib.MGS_OP_SOLVE, Q.device) if work is None else work
+    st = _lib.lib().ls_solve(m, n, prec, _ptr(Q), m, _ptr(R), R.shape[3], _ptr(b), _ptr(x), _ptr(work),
+                             work.numel() * 8, _ptr(info), _stream(Q))
+    _lib.check("ls_solve", st)
+    return x, info
+
+
+def lstsq(A, b):
+    """Least-squares solution of A x = b: MGS on [A b], then back substitution."""
+    f = mgs_qr(A, b)
+    x, info2 = ls_backsolve(f["R"], f["y"])
+    f["x"] = x
+    f["info_backsolve"] = info2
+    return f

@@ -1,0 +1,453 @@
+// MGS QR, least-squares solve and back substitution kernels for gfx950.
+//
+// The factorisation follows Figure 1 of the paper (Section 3) on the matrix
+// augmented with the right-hand side (Equation (1)): for every column k,
+// r_kk = ||a_k||, q_k = a_k / r_kk, and for every later column j (b
+// included) r_kj = q_k^H a_j, a_j -= r_kj q_k.  Every column j receives the
+// projections in the order k = 1, 2, ..., j-1, exactly as in Figure 1; only
+// the schedule differs from the paper's one launch per column (Section 5,
+// Figure 2):
+//
+//   launch t (one per panel of `bw` columns, plus one for b):
+//     block 0   ("panel")    applies the projections of panel t-1 to the
+//               columns of panel t, then factors panel t (norms, square
+//               roots, normalisation, projections inside the panel).  The
+//               block's 4 waves spread the rows; reductions are wave
+//               butterflies plus a 4-way exchange through LDS.
+//     blocks 1+ ("trailing") apply the projections of panel t-1 to every
+//               column beyond panel t: one column per team of `tw` waves,
+//               the column held in registers (rpt rows per lane), q_k read
+//               from L2, reductions by wave butterflies (plus LDS when tw>1).
+//   So panel t is factored while the trailing matrix absorbs panel t-1
+//   (one panel of look-ahead); the kernel boundary orders the panels.
+//
+// Reductions use a fixed butterfly order, so every lane of a team ends with
+// the bitwise identical r_kj and results are reproducible run to run.
+#pragma once
+#include "ddqd.hpp"
+
+namespace mgsq {
+
+constexpr int WG = 256;
+constexpr int NWAVE = WG / 64;
+
+struct StepArgs {
+  int m, n, ncols;  // ncols = n + 1 when b is augmented
+  const double *A;
+  int lda;
+  size_t planeA;
+  const double *b;  // original right-hand side (plane stride m) or null
+  double *Q;
+  int ldq;
+  size_t planeQ;
+  double *R;
+  int ldr;
+  size_t planeR;
+  double *W;  // working copy of the augmented column (plane stride m)
+  double *y;
+  double *rho;
+  int *info;
+  int bw, t, npanel;
+  int rpt, tw;  // trailing role: rows per lane, waves per column
+};
+
+// Column j as read at launch t: on its first touch from A (or b), later
+// from the working storage Q (or W).
+__device__ __forceinline__ const double *col_src(const StepArgs &a, int j, bool first, size_t &plane) {
+  if (j < a.n) {
+    if (first) {
+      plane = a.planeA;
+      return a.A + (size_t)j * a.lda;
+    }
+    plane = a.planeQ;
+    return a.Q + (size_t)j * a.ldq;
+  }
+  plane = (size_t)a.m;
+  return first ? a.b : a.W;
+}
+__device__ __forceinline__ double *col_dst(const StepArgs &a, int j, size_t &plane) {
+  if (j < a.n) {
+    plane = a.planeQ;
+    return a.Q + (size_t)j * a.ldq;
+  }
+  plane = (size_t)a.m;
+  return a.W;
+}
+// r_kj goes to R(k, j), or to y(k) for the augmented column.
+template <class P>
+__device__ __forceinline__ void store_r(const StepArgs &a, int k, int j, const typename P::C &v) {
+  if (j < a.n)
+    P::store(a.R + (size_t)j * a.ldr + k, a.planeR, v);
+  else
+    P::store(a.y + k, (size_t)a.n, v);
+}
+
+template <class P>
+__device__ __forceinline__ void wave_reduce(typename P::Acc &acc) {
+#pragma unroll
+  for (int mask = 32; mask >= 1; mask >>= 1) {
+    typename P::Acc o = P::acc_shfl_xor(acc, mask);
+    P::acc_merge(acc, o);
+  }
+}
+template <class P>
+__device__ __forceinline__ void wave_reduce_re(typename P::Acc &acc) {
+#pragma unroll
+  for (int mask = 32; mask >= 1; mask >>= 1) {
+    typename P::Acc o = P::acc_shfl_xor_re(acc, mask);
+    P::acc_merge_re(acc, o);
+  }
+}
+
+// ------------------------------------------------------------ panel role --
+// Thread tid holds rows i = r*WG + tid (r < RP) of the panel's columns.
+template <class P, int RP, int BWM>
+__device__ void panel_role(const StepArgs &a, typename P::Acc *lds) {
+  using C = typename P::C;
+  using Acc = typename P::Acc;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int k0 = a.t * a.bw;
+  const int nb = min(a.bw, a.n - k0);
+  const bool first = a.t <= 1;
+  if (a.t == 0 && tid == 0) *a.info = 0;
+
+  C col[BWM][RP];
+#pragma unroll
+  for (int c = 0; c < BWM; ++c) {
+    size_t ps;
+    const double *src = col_src(a, k0 + c, first, ps);
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      int i = r * WG + tid;
+      col[c][r] = (c < nb && i < a.m) ? P::load(src + i, ps) : P::czero();
+    }
+  }
+
+  // Batched block reduction of up to BWM accumulators (entries c < cnt).
+  auto block_reduce = [&](Acc(&acc)[BWM], int c_lo, int c_hi) {
+#pragma unroll
+    for (int c = 0; c < BWM; ++c)
+      if (c >= c_lo && c < c_hi) wave_reduce<P>(acc[c]);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < BWM; ++c)
+        if (c >= c_lo && c < c_hi) lds[wave * BWM + c] = acc[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < BWM; ++c) {
+      if (c >= c_lo && c < c_hi) {
+        acc[c] = lds[c];
+#pragma unroll
+        for (int w = 1; w < NWAVE; ++w) P::acc_merge(acc[c], lds[w * BWM + c]);
+      }
+    }
+    __syncthreads();
+  };
+
+  // Look-ahead: projections of panel t-1 onto panel t, k in order.
+  if (a.t > 0) {
+    const int kp0 = k0 - a.bw;
+#pragma unroll 1
+    for (int k = kp0; k < k0; ++k) {
+      const double *qk = a.Q + (size_t)k * a.ldq;
+      C q[RP];
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        int i = r * WG + tid;
+        q[r] = (i < a.m) ? P::load(qk + i, a.planeQ) : P::czero();
+      }
+      Acc acc[BWM];
+#pragma unroll
+      for (int c = 0; c < BWM; ++c) {
+        P::acc_zero(acc[c]);
+        if (c < nb) {
+#pragma unroll
+          for (int r = 0; r < RP; ++r) P::acc_cmulc(acc[c], q[r], col[c][r]);
+        }
+      }
+      block_reduce(acc, 0, nb);
+#pragma unroll
+      for (int c = 0; c < BWM; ++c) {
+        if (c < nb) {
+          C rk = P::acc_value(acc[c]);
+          if (tid == 0) store_r<P>(a, k, k0 + c, rk);
+#pragma unroll
+          for (int r = 0; r < RP; ++r) P::upd(col[c][r], rk, q[r]);
+        }
+      }
+    }
+  }
+
+  // Factor the panel: Figure 1 restricted to columns k0 .. k0+nb-1.
+#pragma unroll
+  for (int c = 0; c < BWM; ++c) {
+    if (c < nb) {
+      const int k = k0 + c;
+      Acc nacc;
+      P::acc_zero(nacc);
+#pragma unroll
+      for (int r = 0; r < RP; ++r) P::acc_abs2(nacc, col[c][r]);
+      wave_reduce_re<P>(nacc);
+      if (lane == 0) lds[wave * BWM + c] = nacc;
+      __syncthreads();
+      Acc s = lds[c];
+#pragma unroll
+      for (int w = 1; w < NWAVE; ++w) P::acc_merge_re(s, lds[w * BWM + c]);
+      __syncthreads();
+      typename P::R s2 = P::acc_value_re(s);
+      if (!P::ok_norm(s2) && tid == 0 && *a.info == 0) *a.info = k + 1;
+      typename P::R rkk = P::sqrt_(s2);
+      typename P::R inv = P::recip(rkk);
+      size_t pq;
+      double *dst = col_dst(a, k, pq);
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        col[c][r] = P::scale(col[c][r], inv);
+        int i = r * WG + tid;
+        if (i < a.m) P::store(dst + i, pq, col[c][r]);
+      }
+      // R(k,k) = r_kk (imaginary +0); R(i,k) = 0 below the diagonal.
+      if (tid == 0) {
+        C d;
+        d.re = rkk;
+        d.im = P::rzero();
+        P::store(a.R + (size_t)k * a.ldr + k, a.planeR, d);
+      }
+      for (int i = k + 1 + tid; i < a.n; i += WG) P::store(a.R + (size_t)k * a.ldr + i, a.planeR, P::czero());
+      // projections of q_k on the rest of the panel
+      Acc acc[BWM];
+#pragma unroll
+      for (int d = 0; d < BWM; ++d) {
+        P::acc_zero(acc[d]);
+        if (d > c && d < nb) {
+#pragma unroll
+          for (int r = 0; r < RP; ++r) P::acc_cmulc(acc[d], col[c][r], col[d][r]);
+        }
+      }
+      if (c + 1 < nb) {
+        block_reduce(acc, c + 1, nb);
+#pragma unroll
+        for (int d = 0; d < BWM; ++d) {
+          if (d > c && d < nb) {
+            C rk = P::acc_value(acc[d]);
+            if (tid == 0) store_r<P>(a, k, k0 + d, rk);
+#pragma unroll
+            for (int r = 0; r < RP; ++r) P::upd(col[d][r], rk, col[c][r]);
+          }
+        }
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------- trailing role --
+// Team `team` of `tw` waves owns column j; lane holds rows
+// i = (r*tw + tw_i)*64 + lane, r < rpt.
+template <class P, int RPT>
+__device__ void trailing_role(const StepArgs &a, int blk, typename P::Acc *lds) {
+  using C = typename P::C;
+  using Acc = typename P::Acc;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tw = a.tw;
+  const int teams = NWAVE / tw;
+  const int team = wave / tw, tw_i = wave % tw;
+  const int kp0 = (a.t - 1) * a.bw;
+  const int kp1 = min(kp0 + a.bw, a.n);
+  const int jstart = min((a.t + 1) * a.bw, a.n);
+  const int j = jstart + blk * teams + team;
+  const bool active = j < a.ncols;
+  const bool first = a.t == 1;
+  const int rpt = a.rpt;
+
+  C col[RPT];
+  size_t ps = 0;
+  const double *src = active ? col_src(a, j, first, ps) : nullptr;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    int i = (r * tw + tw_i) * 64 + lane;
+    col[r] = (active && r < rpt && i < a.m) ? P::load(src + i, ps) : P::czero();
+  }
+
+#pragma unroll 1
+  for (int k = kp0; k < kp1; ++k) {
+    const double *qk = a.Q + (size_t)k * a.ldq;
+    Acc acc;
+    P::acc_zero(acc);
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        int i = (r * tw + tw_i) * 64 + lane;
+        if (r < rpt && i < a.m) P::acc_cmulc(acc, P::load(qk + i, a.planeQ), col[r]);
+      }
+    }
+    wave_reduce<P>(acc);
+    if (tw > 1) {
+      if (lane == 0) lds[wave] = acc;
+      __syncthreads();
+      acc = lds[team * tw];
+      for (int w = 1; w < tw; ++w) P::acc_merge(acc, lds[team * tw + w]);
+      __syncthreads();
+    }
+    if (active) {
+      C rk = P::acc_value(acc);
+      if (tw_i == 0 && lane == 0) store_r<P>(a, k, j, rk);
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        int i = (r * tw + tw_i) * 64 + lane;
+        if (r < rpt && i < a.m) P::upd(col[r], rk, P::load(qk + i, a.planeQ));
+      }
+    }
+  }
+
+  if (active) {
+    size_t pd;
+    double *dst = col_dst(a, j, pd);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      int i = (r * tw + tw_i) * 64 + lane;
+      if (r < rpt && i < a.m) P::store(dst + i, pd, col[r]);
+    }
+  }
+  // After the last panel: z of Equation (1), the norm of the projected b.
+  if (a.t == a.npanel && a.rho != nullptr) {
+    Acc acc;
+    P::acc_zero(acc);
+    if (active && j == a.n) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        int i = (r * tw + tw_i) * 64 + lane;
+        if (r < rpt && i < a.m) P::acc_abs2(acc, col[r]);
+      }
+    }
+    wave_reduce_re<P>(acc);
+    if (tw > 1) {
+      if (lane == 0) lds[wave] = acc;
+      __syncthreads();
+      acc = lds[team * tw];
+      for (int w = 1; w < tw; ++w) P::acc_merge_re(acc, lds[team * tw + w]);
+      __syncthreads();
+    }
+    if (active && j == a.n && tw_i == 0 && lane == 0) {
+      typename P::R s = P::acc_value_re(acc);
+      typename P::R z = P::ok_norm(s) ? P::sqrt_(s) : P::rzero();
+      P::store_real(a.rho, 1, z);
+    }
+  }
+}
+
+template <class P, int RPT, int RP, int BWM>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1))) void mgs_step_kernel(StepArgs a) {
+  __shared__ typename P::Acc lds[NWAVE * BWM];
+  if (a.t < a.npanel) {
+    if (blockIdx.x == 0)
+      panel_role<P, RP, BWM>(a, lds);
+    else
+      trailing_role<P, RPT>(a, blockIdx.x - 1, lds);
+  } else {
+    trailing_role<P, RPT>(a, blockIdx.x, lds);
+  }
+}
+
+
+// ------------------------------------------------- back substitution -----
+// Section 6, Figure 3: for k = n..1, x_k = y_k / r_kk, then y_j -= r_jk x_k
+// for all j < k in parallel.  One block; thread tid keeps y_j for
+// j = s*WG + tid in registers; the reciprocals of the diagonal are formed
+// in parallel up front, so the serial chain per step is one product, one
+// LDS broadcast (double-buffered: one barrier per step) and one update.
+template <class P, int NY>
+__global__ __launch_bounds__(WG) void backsolve_kernel(int n, const double *R, int ldr, size_t planeR,
+                                                        const double *y, double *x, int *info) {
+  using C = typename P::C;
+  using Rl = typename P::R;
+  __shared__ C xs[2];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0x7fffffff;
+  __syncthreads();
+  C yv[NY];
+  Rl inv[NY];
+#pragma unroll
+  for (int s = 0; s < NY; ++s) {
+    int j = s * WG + tid;
+    if (j < n) {
+      yv[s] = P::load(y + j, (size_t)n);
+      C d = P::load(R + (size_t)j * ldr + j, planeR);
+      if (!P::ok_norm(d.re)) atomicMin(&bad, j + 1);
+      inv[s] = P::recip(d.re);
+    } else {
+      yv[s] = P::czero();
+      inv[s] = P::rzero();
+    }
+  }
+  __syncthreads();
+  if (tid == 0) *info = (bad == 0x7fffffff) ? 0 : bad;
+#pragma unroll 1
+  for (int k = n - 1; k >= 0; --k) {
+    const int sk = k / WG, owner = k - sk * WG;
+    if (tid == owner) {
+#pragma unroll
+      for (int s = 0; s < NY; ++s) {
+        if (s == sk) {
+          C xk = P::scale(yv[s], inv[s]);
+          P::store(x + k, (size_t)n, xk);
+          xs[k & 1] = xk;
+        }
+      }
+    }
+    __syncthreads();
+    const C xk = xs[k & 1];
+    const double *Rk = R + (size_t)k * ldr;
+#pragma unroll
+    for (int s = 0; s < NY; ++s) {
+      int j = s * WG + tid;
+      if (s <= sk && j < k) P::upd(yv[s], P::load(Rk + j, planeR), xk);
+    }
+  }
+}
+
+// ------------------------------------------ projections y = Q^H b --------
+// y_k = q_k^H b^(k-1), b^(k) = b^(k-1) - y_k q_k for k = 1..n: the same
+// operations as the augmented column of Equation (1).  One block; b stays
+// in registers (RB rows per thread).
+template <class P, int RB>
+__global__ __launch_bounds__(WG) void project_kernel(int m, int n, const double *Q, int ldq, size_t planeQ,
+                                                      const double *b, double *y) {
+  using C = typename P::C;
+  using Acc = typename P::Acc;
+  __shared__ Acc lds[NWAVE];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  C bv[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    int i = r * WG + tid;
+    bv[r] = (i < m) ? P::load(b + i, (size_t)m) : P::czero();
+  }
+#pragma unroll 1
+  for (int k = 0; k < n; ++k) {
+    const double *qk = Q + (size_t)k * ldq;
+    C q[RB];
+    Acc acc;
+    P::acc_zero(acc);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      int i = r * WG + tid;
+      q[r] = (i < m) ? P::load(qk + i, planeQ) : P::czero();
+      P::acc_cmulc(acc, q[r], bv[r]);
+    }
+    wave_reduce<P>(acc);
+    if (lane == 0) lds[wave] = acc;
+    __syncthreads();
+    acc = lds[0];
+#pragma unroll
+    for (int w = 1; w < NWAVE; ++w) P::acc_merge(acc, lds[w]);
+    __syncthreads();
+    C yk = P::acc_value(acc);
+    if (tid == 0) P::store(y + k, (size_t)n, yk);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) P::upd(bv[r], yk, q[r]);
+  }
+}
+
+}  // namespace mgsq

@@ -1,0 +1,228 @@
+// C ABI of the MGS least-squares library (declared in include/mgsqr.h):
+// argument checks, launch-shape selection and kernel launches.  No
+// allocation, no host<->device copies, no synchronisation.
+#include "../../include/mgsqr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mgs_kernels.hpp"
+
+using namespace mgsq;
+
+namespace {
+
+bool aligned8(const void *p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+int max_rows(int prec) { return prec == 2 ? MGS_MAX_ROWS_DD : MGS_MAX_ROWS_QD; }
+int pow2_at_least(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Launch shape of one factorisation:
+//   trailing role: tw waves per column so that rpt = ceil(m / (64 tw)) rows
+//   per lane fit the register budget (dd 16, qd 8);
+//   panel role: RP rows per thread (power of two >= m / 256), panel width
+//   bw = min(BWmax, elements-per-thread budget / RP).
+struct Shape {
+  int tw, rpt, rp, bw;
+};
+Shape choose_shape(int m, int prec) {
+  Shape s;
+  const int rpt_max = prec == 2 ? 16 : 8;
+  s.tw = pow2_at_least(ceil_div(m, 64 * rpt_max));
+  s.rpt = ceil_div(m, 64 * s.tw);
+  s.rp = pow2_at_least(ceil_div(m, WG));
+  const int budget = prec == 2 ? 8 : 4, bwmax = prec == 2 ? 8 : 4;
+  s.bw = budget / s.rp < bwmax ? budget / s.rp : bwmax;
+  if (s.bw < 1) s.bw = 1;
+  return s;
+}
+
+template <class P, int RPT, int RP, int BWM>
+int launch_steps(StepArgs a, hipStream_t st) {
+  const int teams = NWAVE / a.tw;
+  const int last = a.ncols > a.n ? a.npanel : a.npanel - 1;
+  for (int t = 0; t <= last; ++t) {
+    a.t = t;
+    const int jstart = (t + 1) * a.bw < a.n ? (t + 1) * a.bw : a.n;
+    const int ntrail = t >= 1 ? a.ncols - jstart : 0;
+    const int tblocks = ntrail > 0 ? ceil_div(ntrail, teams) : 0;
+    const int grid = (t < a.npanel ? 1 : 0) + tblocks;
+    if (grid == 0) continue;
+    hipLaunchKernelGGL((mgs_step_kernel<P, RPT, RP, BWM>), dim3(grid), dim3(WG), 0, st, a);
+    if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
+  }
+  return MGS_OK;
+}
+
+template <class P, int RPT>
+int dispatch_rp(const StepArgs &a, int rp, hipStream_t st) {
+  constexpr int budget = P::L == 2 ? 8 : 4;
+  constexpr int bwmax = P::L == 2 ? 8 : 4;
+#define MGS_RP_CASE(R)                                                        \
+  case R: {                                                                   \
+    constexpr int bwm = (budget / R < bwmax ? budget / R : bwmax) > 0 ? (budget / R < bwmax ? budget / R : bwmax) : 1; \
+    return launch_steps<P, RPT, R, bwm>(a, st);                               \
+  }
+  switch (rp) {
+    MGS_RP_CASE(1)
+    MGS_RP_CASE(2)
+    MGS_RP_CASE(4)
+    MGS_RP_CASE(8)
+  }
+  if constexpr (P::L == 2) {
+    if (rp == 16) return launch_steps<P, RPT, 16, 1>(a, st);
+  }
+#undef MGS_RP_CASE
+  return MGS_ERR_DIMS;
+}
+
+template <class P>
+int backsolve_launch(int n, const double *R, int ldr, const double *y, double *x, int *info, hipStream_t st) {
+  const int ny = pow2_at_least(ceil_div(n, WG));
+  const size_t planeR = (size_t)ldr * n;
+#define MGS_NY_CASE(NYV)                                                                                  \
+  case NYV:                                                                                               \
+    hipLaunchKernelGGL((backsolve_kernel<P, NYV>), dim3(1), dim3(WG), 0, st, n, R, ldr, planeR, y, x, info); \
+    break;
+  switch (ny) {
+    MGS_NY_CASE(1)
+    MGS_NY_CASE(2)
+    MGS_NY_CASE(4)
+    MGS_NY_CASE(8)
+    MGS_NY_CASE(16)
+    default:
+      return MGS_ERR_DIMS;
+  }
+#undef MGS_NY_CASE
+  return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
+}
+
+template <class P>
+int project_launch(int m, int n, const double *Q, int ldq, const double *b, double *y, hipStream_t st) {
+  const int rb = pow2_at_least(ceil_div(m, WG));
+  const size_t planeQ = (size_t)ldq * n;
+#define MGS_RB_CASE(RBV)                                                                                     \
+  case RBV:                                                                                                  \
+    hipLaunchKernelGGL((project_kernel<P, RBV>), dim3(1), dim3(WG), 0, st, m, n, Q, ldq, planeQ, b, y);       \
+    break;
+  switch (rb) {
+    MGS_RB_CASE(1)
+    MGS_RB_CASE(2)
+    MGS_RB_CASE(4)
+    MGS_RB_CASE(8)
+    MGS_RB_CASE(16)
+    default:
+      return MGS_ERR_DIMS;
+  }
+#undef MGS_RB_CASE
+  return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
+}
+
+size_t qr_work_bytes(int m, int prec) { return round256(sizeof(double) * 2 * (size_t)prec * m); }
+size_t solve_work_bytes(int n, int prec) { return round256(sizeof(double) * 2 * (size_t)prec * n); }
+
+}  // namespace
+
+extern "C" {
+
+int mgs_abi_version(void) { return MGS_ABI_VERSION; }
+
+const char *mgs_status_string(int status) {
+  switch (status) {
+    case MGS_OK: return "success";
+    case MGS_ERR_DIMS: return "invalid dimensions (need 1 <= n <= m <= max rows, ld >= rows)";
+    case MGS_ERR_POINTER: return "null, misaligned or illegally aliased pointer";
+    case MGS_ERR_PREC: return "unsupported precision (prec must be 2 or 4)";
+    case MGS_ERR_WORKSPACE: return "workspace too small";
+    case MGS_ERR_LAUNCH: return "kernel launch failed";
+    case MGS_ERR_UNSUPPORTED: return "unsupported operation";
+  }
+  return "unknown status";
+}
+
+int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes) {
+  if (prec != 2 && prec != 4) return MGS_ERR_PREC;
+  if (n < 1 || m < n || m > max_rows(prec)) return MGS_ERR_DIMS;
+  if (!bytes) return MGS_ERR_POINTER;
+  switch (op) {
+    case MGS_OP_QR: *bytes = qr_work_bytes(m, prec); return MGS_OK;
+    case MGS_OP_SOLVE: *bytes = solve_work_bytes(n, prec); return MGS_OK;
+  }
+  return MGS_ERR_UNSUPPORTED;
+}
+
+int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq, double *R, int ldr,
+           const double *b, double *y, double *rho, void *work, size_t work_bytes, int *info,
+           mgs_stream_t stream) {
+  if (prec != 2 && prec != 4) return MGS_ERR_PREC;
+  if (n < 1 || m < n || m > max_rows(prec) || lda < m || ldq < m || ldr < n) return MGS_ERR_DIMS;
+  if (!aligned8(A) || !aligned8(Q) || !aligned8(R) || !aligned8(info)) return MGS_ERR_POINTER;
+  if (Q == A && ldq != lda) return MGS_ERR_POINTER;
+  if (rho && !aligned8(rho)) return MGS_ERR_POINTER;
+  if (b) {
+    if (!aligned8(b) || !aligned8(y) || !aligned8(work)) return MGS_ERR_POINTER;
+    if (work_bytes < qr_work_bytes(m, prec)) return MGS_ERR_WORKSPACE;
+  }
+  Shape sh = choose_shape(m, prec);
+  StepArgs a;
+  a.m = m;
+  a.n = n;
+  a.ncols = n + (b ? 1 : 0);
+  a.A = A;
+  a.lda = lda;
+  a.planeA = (size_t)lda * n;
+  a.b = b;
+  a.Q = Q;
+  a.ldq = ldq;
+  a.planeQ = (size_t)ldq * n;
+  a.R = R;
+  a.ldr = ldr;
+  a.planeR = (size_t)ldr * n;
+  a.W = b ? static_cast<double *>(work) : nullptr;
+  a.y = b ? y : nullptr;
+  a.rho = b ? rho : nullptr;
+  a.info = info;
+  a.bw = sh.bw;
+  a.t = 0;
+  a.npanel = ceil_div(n, sh.bw);
+  a.rpt = sh.rpt;
+  a.tw = sh.tw;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (prec == 2) return dispatch_rp<PrecDD, 16>(a, sh.rp, st);
+  return dispatch_rp<PrecQD, 8>(a, sh.rp, st);
+}
+
+int ls_backsolve(int n, int prec, const double *R, int ldr, const double *y, double *x, int *info,
+                 mgs_stream_t stream) {
+  if (prec != 2 && prec != 4) return MGS_ERR_PREC;
+  if (n < 1 || n > max_rows(prec) || ldr < n) return MGS_ERR_DIMS;
+  if (!aligned8(R) || !aligned8(y) || !aligned8(x) || !aligned8(info)) return MGS_ERR_POINTER;
+  if (x == y) return MGS_ERR_POINTER;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (prec == 2) return backsolve_launch<PrecDD>(n, R, ldr, y, x, info, st);
+  return backsolve_launch<PrecQD>(n, R, ldr, y, x, info, st);
+}
+
+int ls_solve(int m, int n, int prec, const double *Q, int ldq, const double *R, int ldr,
+             const double *b, double *x, void *work, size_t work_bytes, int *info,
+             mgs_stream_t stream) {
+  if (prec != 2 && prec != 4) return MGS_ERR_PREC;
+  if (n < 1 || m < n || m > max_rows(prec) || ldq < m || ldr < n) return MGS_ERR_DIMS;
+  if (!aligned8(Q) || !aligned8(R) || !aligned8(b) || !aligned8(x) || !aligned8(info) || !aligned8(work))
+    return MGS_ERR_POINTER;
+  if (work_bytes < solve_work_bytes(n, prec)) return MGS_ERR_WORKSPACE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  double *y = static_cast<double *>(work);
+  int rc = prec == 2 ? project_launch<PrecDD>(m, n, Q, ldq, b, y, st) : project_launch<PrecQD>(m, n, Q, ldq, b, y, st);
+  if (rc != MGS_OK) return rc;
+  if (prec == 2) return backsolve_launch<PrecDD>(n, R, ldr, y, x, info, st);
+  return backsolve_launch<PrecQD>(n, R, ldr, y, x, info, st);
+}
+
+}  // extern "C"

@@ -163,27 +163,31 @@ def _two_prod(a, b):
 def dd_matvec_dx(A, x):
     """b = A x for dd A (2,2,n,m) and FP64 x (1,2,n), to dd accuracy.
 
-    Exact leading products and sums (TwoProd, TwoSum) with the rounding
-    errors and the low-limb products gathered in one FP64 accumulator per
-    component, then renormalised (compensated dot product).
+    Leading products split exactly (TwoProd), summed over the columns by a
+    pairwise TwoSum tree; every rounding error and every low-limb product is
+    gathered in one FP64 array; the pair is renormalised at the end.
     """
     _, _, n, m = A.shape
-    xr, xi = x[0, 0], x[0, 1]
-    S = [np.zeros(m), np.zeros(m)]
-    Cc = [np.zeros(m), np.zeros(m)]
-    for j in range(n):
-        ahr, ahi, alr, ali = A[0, 0, j], A[0, 1, j], A[1, 0, j], A[1, 1, j]
-        # real: ar xr - ai xi ; imag: ar xi + ai xr
-        for comp, terms in ((0, ((ahr, alr, xr[j], 1.0), (ahi, ali, xi[j], -1.0))),
-                            (1, ((ahr, alr, xi[j], 1.0), (ahi, ali, xr[j], 1.0)))):
-            for h, lo, xv, sg in terms:
-                p, e = _two_prod(h, sg * xv)
-                S[comp], t = _two_sum(S[comp], p)
-                Cc[comp] = Cc[comp] + (e + t + lo * (sg * xv))
+    xr, xi = x[0, 0][:, None], x[0, 1][:, None]
     b = np.zeros((2, 2, m))
     for comp in range(2):
-        s, e = _two_sum(S[comp], Cc[comp])
-        b[0, comp], b[1, comp] = s, e
+        if comp == 0:  # ar xr - ai xi
+            terms = ((A[0, 0], A[1, 0], xr), (A[0, 1], A[1, 1], -xi))
+        else:  # ar xi + ai xr
+            terms = ((A[0, 0], A[1, 0], xi), (A[0, 1], A[1, 1], xr))
+        hs, lows = [], 0.0
+        for h, lo, xv in terms:
+            p, e = _two_prod(h, np.broadcast_to(xv, h.shape))
+            hs.append(p)
+            lows = lows + np.sum(e + lo * xv, axis=0)
+        S = np.concatenate(hs, axis=0)
+        while S.shape[0] > 1:
+            if S.shape[0] % 2:
+                S = np.concatenate([S, np.zeros((1, m))], axis=0)
+            s, t = _two_sum(S[0::2], S[1::2])
+            lows = lows + np.sum(t, axis=0)
+            S = s
+        b[0, comp], b[1, comp] = _two_sum(S[0], lows)
     return b
 
 
@@ -216,9 +220,8 @@ def config3(system=0, m=1024, n=1024):
     c = 10.0 ** s
     A = np.zeros((2, 2, n, m))
     for p in range(2):
-        h, lo = _two_prod(c[:, None], G[p])
-        A[0, p], A[1, p] = h, lo
-    A[:] = np.stack([np.stack(normalize([A[0, p], A[1, p]])) for p in range(2)], axis=1)
+        # TwoProd output is a normalised dd: |lo| <= ulp(hi) / 2
+        A[0, p], A[1, p] = _two_prod(c[:, None], G[p])
     xg = rng(3, system, 1)
     x = np.zeros((1, 2, n))
     x[0] = xg.standard_normal((2, n))

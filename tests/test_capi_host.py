@@ -1,0 +1,111 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+declared in include/mgsqr.h, and rejects bad arguments before any launch.
+
+No call here passes argument validation, so no kernel is ever launched.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1210_0800_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mgsqr.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for f in _lib.EXPORTS:
+        assert f in names, f
+    assert set(names) == set(_lib.EXPORTS), names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert L.mgs_abi_version() == 1
+
+
+def test_status_strings():
+    L = _lib.lib()
+    for st in range(0, -7, -1):
+        s = L.mgs_status_string(st).decode()
+        assert s and s != "unknown status"
+    assert L.mgs_status_string(-99).decode() == "unknown status"
+
+
+def test_workspace_sizes():
+    assert _lib.workspace_size(32, 32, 2, _lib.MGS_OP_QR) == 2 * 2 * 32 * 8
+    assert _lib.workspace_size(320, 256, 4, _lib.MGS_OP_QR) == 2 * 4 * 320 * 8
+    assert _lib.workspace_size(100, 10, 2, _lib.MGS_OP_SOLVE) == 512
+    with pytest.raises(_lib.MgsError):
+        _lib.workspace_size(10, 11, 2, _lib.MGS_OP_QR)
+    with pytest.raises(_lib.MgsError):
+        _lib.workspace_size(10, 10, 3, _lib.MGS_OP_QR)
+    with pytest.raises(_lib.MgsError):
+        _lib.workspace_size(10, 10, 2, 7)
+    with pytest.raises(_lib.MgsError):
+        _lib.workspace_size(4097, 10, 2, _lib.MGS_OP_QR)
+    with pytest.raises(_lib.MgsError):
+        _lib.workspace_size(2049, 10, 4, _lib.MGS_OP_QR)
+
+
+FAKE = 0x10000  # aligned, never dereferenced: every call below fails validation first
+ODD = 0x10004 + 1
+
+
+def _qr(m=8, n=4, prec=2, A=FAKE, lda=8, Q=FAKE + 4096, ldq=8, R=FAKE + 8192, ldr=4, b=None, y=None,
+        rho=None, work=None, wb=0, info=FAKE + 12288):
+    return _lib.lib().mgs_qr(m, n, prec, A, lda, Q, ldq, R, ldr, b, y, rho, work, wb, info, None)
+
+
+def test_mgs_qr_rejects_bad_arguments():
+    assert _qr(prec=3) == -3
+    assert _qr(prec=1) == -3
+    assert _qr(m=3, n=4) == -1
+    assert _qr(n=0) == -1
+    assert _qr(lda=7) == -1
+    assert _qr(ldq=7) == -1
+    assert _qr(ldr=3) == -1
+    assert _qr(m=4097, lda=4097, ldq=4097) == -1
+    assert _qr(prec=4, m=2049, lda=2049, ldq=2049) == -1
+    assert _qr(A=None) == -2
+    assert _qr(A=ODD) == -2
+    assert _qr(info=None) == -2
+    assert _qr(Q=FAKE, A=FAKE, ldq=9, lda=8) in (-1, -2)
+    # b given: y and workspace required
+    assert _qr(b=FAKE + 16384, y=None, work=FAKE + 20480, wb=1024) == -2
+    assert _qr(b=FAKE + 16384, y=FAKE + 24576, work=None, wb=1024) == -2
+    assert _qr(b=FAKE + 16384, y=FAKE + 24576, work=FAKE + 20480, wb=8) == -4
+
+
+def test_ls_solve_and_backsolve_reject_bad_arguments():
+    L = _lib.lib()
+    assert L.ls_solve(8, 4, 3, FAKE, 8, FAKE, 4, FAKE, FAKE, FAKE, 4096, FAKE, None) == -3
+    assert L.ls_solve(3, 4, 2, FAKE, 8, FAKE, 4, FAKE, FAKE, FAKE, 4096, FAKE, None) == -1
+    assert L.ls_solve(8, 4, 2, FAKE, 8, FAKE, 4, None, FAKE, FAKE, 4096, FAKE, None) == -2
+    assert L.ls_solve(8, 4, 2, FAKE, 8, FAKE, 4, FAKE, FAKE + 64, FAKE + 128, 8, FAKE, None) == -4
+    assert L.ls_backsolve(4, 2, FAKE, 3, FAKE, FAKE + 64, FAKE, None) == -1
+    assert L.ls_backsolve(0, 2, FAKE, 4, FAKE, FAKE + 64, FAKE, None) == -1
+    assert L.ls_backsolve(4, 5, FAKE, 4, FAKE, FAKE + 64, FAKE, None) == -3
+    assert L.ls_backsolve(4, 2, FAKE, 4, FAKE, FAKE, FAKE, None) == -2  # x aliases y
+    assert L.ls_backsolve(4, 2, None, 4, FAKE, FAKE + 64, FAKE, None) == -2
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+
+    from paper_1210_0800_amd import api
+
+    A = torch.zeros(2, 2, 3, 4, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        api.mgs_qr(A)
