@@ -24,12 +24,33 @@
 // Reductions use a fixed butterfly order, so every lane of a team ends with
 // the bitwise identical r_kj and results are reproducible run to run.
 #pragma once
+#include <utility>
+
 #include "ddqd.hpp"
 
 namespace mgsq {
 
 constexpr int WG = 256;
 constexpr int NWAVE = WG / 64;
+
+// Compile-time loop: f(std::integral_constant<int, i>) for i = 0..N-1, so
+// that register arrays indexed by i keep static indices however large the
+// body is.
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Block barrier for LDS traffic only: waits for this wave's LDS operations,
+// then s_barrier.  Unlike __syncthreads() it does not wait for outstanding
+// global loads, so register loads of a column can stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 struct StepArgs {
   int m, n, ncols;  // ncols = n + 1 when b is augmented
@@ -48,8 +69,41 @@ struct StepArgs {
   double *rho;
   int *info;
   int bw, t, npanel;
-  int rpt, tw;  // trailing role: rows per lane, waves per column
+  int mpad;    // rows padded to the launch shape: LDS plane stride, multiple of WG
+  int qstage;  // q vectors staged in LDS at a time
 };
+
+// Copy q_k0 .. q_{k0+cnt-1} from Q into LDS, layout [vector][plane][row]
+// with plane stride mpad; rows m .. mpad-1 are zero.  Up to 16 loads per
+// thread are in flight before the LDS stores.
+template <class P>
+__device__ __forceinline__ void stage_q(const StepArgs &a, int k0, int cnt, double *qs) {
+  const int tid = threadIdx.x;
+  const int chunks = a.mpad / WG;
+  const int total = cnt * 2 * P::L * chunks;
+  for (int base = 0; base < total; base += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = base + u;  // uniform across the block
+      v[u] = 0.0;
+      if (e < total) {
+        const int cp = e / chunks, ch = e - cp * chunks;
+        const int c = cp / (2 * P::L), p = cp - c * (2 * P::L);
+        const int row = ch * WG + tid;
+        if (row < a.m) v[u] = a.Q[(size_t)(k0 + c) * a.ldq + (size_t)p * a.planeQ + row];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = base + u;
+      if (e < total) {
+        const int cp = e / chunks, ch = e - cp * chunks;
+        qs[(size_t)cp * a.mpad + ch * WG + tid] = v[u];
+      }
+    }
+  }
+}
 
 // Column j as read at launch t: on its first touch from A (or b), later
 // from the working storage Q (or W).
@@ -99,10 +153,36 @@ __device__ __forceinline__ void wave_reduce_re(typename P::Acc &acc) {
   }
 }
 
+// Batched block reduction of the accumulators c in [c_lo, c_hi): wave
+// butterflies, then the NWAVE partials combined in wave order through LDS.
+template <class P, int BWM>
+__device__ __forceinline__ void block_reduce(typename P::Acc (&acc)[BWM], int c_lo, int c_hi,
+                                             typename P::Acc *lds, int wave, int lane) {
+#pragma unroll
+  for (int c = 0; c < BWM; ++c)
+    if (c >= c_lo && c < c_hi) wave_reduce<P>(acc[c]);
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < BWM; ++c)
+      if (c >= c_lo && c < c_hi) lds[wave * BWM + c] = acc[c];
+  }
+  lds_barrier();
+#pragma unroll
+  for (int c = 0; c < BWM; ++c) {
+    if (c >= c_lo && c < c_hi) {
+      acc[c] = lds[c];
+#pragma unroll
+      for (int w = 1; w < NWAVE; ++w) P::acc_merge(acc[c], lds[w * BWM + c]);
+    }
+  }
+  lds_barrier();
+}
+
 // ------------------------------------------------------------ panel role --
-// Thread tid holds rows i = r*WG + tid (r < RP) of the panel's columns.
+// Thread tid holds rows i = r*WG + tid (r < RP) of the panel's columns;
+// rows beyond m are zero, so the inner loops carry no bounds tests.
 template <class P, int RP, int BWM>
-__device__ void panel_role(const StepArgs &a, typename P::Acc *lds) {
+__device__ void panel_role(const StepArgs &a, typename P::Acc *lds, double *qs) {
   using C = typename P::C;
   using Acc = typename P::Acc;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -123,65 +203,49 @@ __device__ void panel_role(const StepArgs &a, typename P::Acc *lds) {
     }
   }
 
-  // Batched block reduction of up to BWM accumulators (entries c < cnt).
-  auto block_reduce = [&](Acc(&acc)[BWM], int c_lo, int c_hi) {
-#pragma unroll
-    for (int c = 0; c < BWM; ++c)
-      if (c >= c_lo && c < c_hi) wave_reduce<P>(acc[c]);
-    if (lane == 0) {
-#pragma unroll
-      for (int c = 0; c < BWM; ++c)
-        if (c >= c_lo && c < c_hi) lds[wave * BWM + c] = acc[c];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < BWM; ++c) {
-      if (c >= c_lo && c < c_hi) {
-        acc[c] = lds[c];
-#pragma unroll
-        for (int w = 1; w < NWAVE; ++w) P::acc_merge(acc[c], lds[w * BWM + c]);
-      }
-    }
-    __syncthreads();
-  };
-
-  // Look-ahead: projections of panel t-1 onto panel t, k in order.
+  // Look-ahead: projections of panel t-1 onto panel t, k in order, the
+  // q vectors read from LDS.
   if (a.t > 0) {
     const int kp0 = k0 - a.bw;
 #pragma unroll 1
-    for (int k = kp0; k < k0; ++k) {
-      const double *qk = a.Q + (size_t)k * a.ldq;
-      C q[RP];
+    for (int kc = kp0; kc < k0; kc += a.qstage) {
+      const int cnt = min(a.qstage, k0 - kc);
+      lds_barrier();
+      stage_q<P>(a, kc, cnt, qs);
+      lds_barrier();
+#pragma unroll 1
+      for (int cc = 0; cc < cnt; ++cc) {
+        const int k = kc + cc;
+        const double *qk = qs + (size_t)cc * 2 * P::L * a.mpad;
+        C q[RP];
 #pragma unroll
-      for (int r = 0; r < RP; ++r) {
-        int i = r * WG + tid;
-        q[r] = (i < a.m) ? P::load(qk + i, a.planeQ) : P::czero();
-      }
-      Acc acc[BWM];
+        for (int r = 0; r < RP; ++r) q[r] = P::load(qk + r * WG + tid, (size_t)a.mpad);
+        Acc acc[BWM];
 #pragma unroll
-      for (int c = 0; c < BWM; ++c) {
-        P::acc_zero(acc[c]);
-        if (c < nb) {
+        for (int c = 0; c < BWM; ++c) {
+          P::acc_zero(acc[c]);
+          if (c < nb) {
 #pragma unroll
-          for (int r = 0; r < RP; ++r) P::acc_cmulc(acc[c], q[r], col[c][r]);
+            for (int r = 0; r < RP; ++r) P::acc_cmulc(acc[c], q[r], col[c][r]);
+          }
         }
-      }
-      block_reduce(acc, 0, nb);
+        block_reduce<P, BWM>(acc, 0, nb, lds, wave, lane);
 #pragma unroll
-      for (int c = 0; c < BWM; ++c) {
-        if (c < nb) {
-          C rk = P::acc_value(acc[c]);
-          if (tid == 0) store_r<P>(a, k, k0 + c, rk);
+        for (int c = 0; c < BWM; ++c) {
+          if (c < nb) {
+            C rk = P::acc_value(acc[c]);
+            if (tid == 0) store_r<P>(a, k, k0 + c, rk);
 #pragma unroll
-          for (int r = 0; r < RP; ++r) P::upd(col[c][r], rk, q[r]);
+            for (int r = 0; r < RP; ++r) P::upd(col[c][r], rk, q[r]);
+          }
         }
       }
     }
   }
 
   // Factor the panel: Figure 1 restricted to columns k0 .. k0+nb-1.
-#pragma unroll
-  for (int c = 0; c < BWM; ++c) {
+  static_for<BWM>([&](auto cI) __attribute__((always_inline)) {
+    constexpr int c = decltype(cI)::value;
     if (c < nb) {
       const int k = k0 + c;
       Acc nacc;
@@ -190,11 +254,11 @@ __device__ void panel_role(const StepArgs &a, typename P::Acc *lds) {
       for (int r = 0; r < RP; ++r) P::acc_abs2(nacc, col[c][r]);
       wave_reduce_re<P>(nacc);
       if (lane == 0) lds[wave * BWM + c] = nacc;
-      __syncthreads();
+      lds_barrier();
       Acc s = lds[c];
 #pragma unroll
       for (int w = 1; w < NWAVE; ++w) P::acc_merge_re(s, lds[w * BWM + c]);
-      __syncthreads();
+      lds_barrier();
       typename P::R s2 = P::acc_value_re(s);
       if (!P::ok_norm(s2) && tid == 0 && *a.info == 0) *a.info = k + 1;
       typename P::R rkk = P::sqrt_(s2);
@@ -226,7 +290,7 @@ __device__ void panel_role(const StepArgs &a, typename P::Acc *lds) {
         }
       }
       if (c + 1 < nb) {
-        block_reduce(acc, c + 1, nb);
+        block_reduce<P, BWM>(acc, c + 1, nb, lds, wave, lane);
 #pragma unroll
         for (int d = 0; d < BWM; ++d) {
           if (d > c && d < nb) {
@@ -238,64 +302,67 @@ __device__ void panel_role(const StepArgs &a, typename P::Acc *lds) {
         }
       }
     }
-  }
+  });
 }
 
 // --------------------------------------------------------- trailing role --
-// Team `team` of `tw` waves owns column j; lane holds rows
-// i = (r*tw + tw_i)*64 + lane, r < rpt.
-template <class P, int RPT>
-__device__ void trailing_role(const StepArgs &a, int blk, typename P::Acc *lds) {
+// A team of TW waves owns column j; lane holds rows
+// i = (r*TW + tw_i)*64 + lane, r < RPT (rows beyond m zero).
+template <class P, int RPT, int TW>
+__device__ void trailing_role(const StepArgs &a, int blk, typename P::Acc *lds, double *qs) {
   using C = typename P::C;
   using Acc = typename P::Acc;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int tw = a.tw;
-  const int teams = NWAVE / tw;
-  const int team = wave / tw, tw_i = wave % tw;
+  constexpr int TEAMS = NWAVE / TW;
+  const int team = wave / TW, tw_i = wave % TW;
   const int kp0 = (a.t - 1) * a.bw;
   const int kp1 = min(kp0 + a.bw, a.n);
   const int jstart = min((a.t + 1) * a.bw, a.n);
-  const int j = jstart + blk * teams + team;
+  const int j = jstart + blk * TEAMS + team;
   const bool active = j < a.ncols;
   const bool first = a.t == 1;
-  const int rpt = a.rpt;
 
   C col[RPT];
   size_t ps = 0;
   const double *src = active ? col_src(a, j, first, ps) : nullptr;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    int i = (r * tw + tw_i) * 64 + lane;
-    col[r] = (active && r < rpt && i < a.m) ? P::load(src + i, ps) : P::czero();
+    int i = (r * TW + tw_i) * 64 + lane;
+    col[r] = (active && i < a.m) ? P::load(src + i, ps) : P::czero();
   }
 
 #pragma unroll 1
-  for (int k = kp0; k < kp1; ++k) {
-    const double *qk = a.Q + (size_t)k * a.ldq;
-    Acc acc;
-    P::acc_zero(acc);
-    if (active) {
+  for (int kc = kp0; kc < kp1; kc += a.qstage) {
+    const int cnt = min(a.qstage, kp1 - kc);
+    lds_barrier();
+    stage_q<P>(a, kc, cnt, qs);
+    lds_barrier();
+#pragma unroll 1
+    for (int cc = 0; cc < cnt; ++cc) {
+      const int k = kc + cc;
+      const double *qk = qs + (size_t)cc * 2 * P::L * a.mpad;
+      Acc acc;
+      P::acc_zero(acc);
+      if (active) {
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        int i = (r * tw + tw_i) * 64 + lane;
-        if (r < rpt && i < a.m) P::acc_cmulc(acc, P::load(qk + i, a.planeQ), col[r]);
+        for (int r = 0; r < RPT; ++r)
+          P::acc_cmulc(acc, P::load(qk + (r * TW + tw_i) * 64 + lane, (size_t)a.mpad), col[r]);
       }
-    }
-    wave_reduce<P>(acc);
-    if (tw > 1) {
-      if (lane == 0) lds[wave] = acc;
-      __syncthreads();
-      acc = lds[team * tw];
-      for (int w = 1; w < tw; ++w) P::acc_merge(acc, lds[team * tw + w]);
-      __syncthreads();
-    }
-    if (active) {
-      C rk = P::acc_value(acc);
-      if (tw_i == 0 && lane == 0) store_r<P>(a, k, j, rk);
+      wave_reduce<P>(acc);
+      if (TW > 1) {
+        if (lane == 0) lds[wave] = acc;
+        lds_barrier();
+        acc = lds[team * TW];
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        int i = (r * tw + tw_i) * 64 + lane;
-        if (r < rpt && i < a.m) P::upd(col[r], rk, P::load(qk + i, a.planeQ));
+        for (int w = 1; w < TW; ++w) P::acc_merge(acc, lds[team * TW + w]);
+        lds_barrier();
+      }
+      if (active) {
+        C rk = P::acc_value(acc);
+        if (tw_i == 0 && lane == 0) store_r<P>(a, k, j, rk);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+          P::upd(col[r], rk, P::load(qk + (r * TW + tw_i) * 64 + lane, (size_t)a.mpad));
       }
     }
   }
@@ -305,8 +372,8 @@ __device__ void trailing_role(const StepArgs &a, int blk, typename P::Acc *lds) 
     double *dst = col_dst(a, j, pd);
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-      int i = (r * tw + tw_i) * 64 + lane;
-      if (r < rpt && i < a.m) P::store(dst + i, pd, col[r]);
+      int i = (r * TW + tw_i) * 64 + lane;
+      if (i < a.m) P::store(dst + i, pd, col[r]);
     }
   }
   // After the last panel: z of Equation (1), the norm of the projected b.
@@ -315,18 +382,16 @@ __device__ void trailing_role(const StepArgs &a, int blk, typename P::Acc *lds) 
     P::acc_zero(acc);
     if (active && j == a.n) {
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        int i = (r * tw + tw_i) * 64 + lane;
-        if (r < rpt && i < a.m) P::acc_abs2(acc, col[r]);
-      }
+      for (int r = 0; r < RPT; ++r) P::acc_abs2(acc, col[r]);
     }
     wave_reduce_re<P>(acc);
-    if (tw > 1) {
+    if (TW > 1) {
       if (lane == 0) lds[wave] = acc;
-      __syncthreads();
-      acc = lds[team * tw];
-      for (int w = 1; w < tw; ++w) P::acc_merge_re(acc, lds[team * tw + w]);
-      __syncthreads();
+      lds_barrier();
+      acc = lds[team * TW];
+#pragma unroll
+      for (int w = 1; w < TW; ++w) P::acc_merge_re(acc, lds[team * TW + w]);
+      lds_barrier();
     }
     if (active && j == a.n && tw_i == 0 && lane == 0) {
       typename P::R s = P::acc_value_re(acc);
@@ -336,19 +401,19 @@ __device__ void trailing_role(const StepArgs &a, int blk, typename P::Acc *lds) 
   }
 }
 
-template <class P, int RPT, int RP, int BWM>
+template <class P, int RPT, int TW, int RP, int BWM>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1))) void mgs_step_kernel(StepArgs a) {
   __shared__ typename P::Acc lds[NWAVE * BWM];
+  extern __shared__ double qs[];
   if (a.t < a.npanel) {
     if (blockIdx.x == 0)
-      panel_role<P, RP, BWM>(a, lds);
+      panel_role<P, RP, BWM>(a, lds, qs);
     else
-      trailing_role<P, RPT>(a, blockIdx.x - 1, lds);
+      trailing_role<P, RPT, TW>(a, blockIdx.x - 1, lds, qs);
   } else {
-    trailing_role<P, RPT>(a, blockIdx.x, lds);
+    trailing_role<P, RPT, TW>(a, blockIdx.x, lds, qs);
   }
 }
-
 
 // ------------------------------------------------- back substitution -----
 // Section 6, Figure 3: for k = n..1, x_k = y_k / r_kk, then y_j -= r_jk x_k

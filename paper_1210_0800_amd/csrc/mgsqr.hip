@@ -23,62 +23,94 @@ int pow2_at_least(int v) {
 }
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// Launch shape of one factorisation:
-//   trailing role: tw waves per column so that rpt = ceil(m / (64 tw)) rows
-//   per lane fit the register budget (dd 16, qd 8);
-//   panel role: RP rows per thread (power of two >= m / 256), panel width
-//   bw = min(BWmax, elements-per-thread budget / RP).
+// Launch shape of one factorisation (rows padded to the shape, zeros beyond m):
+//   trailing role: a team of TW waves per column, RPT rows per lane
+//     (RPT a power of two, at most 16 for dd and 8 for qd, so that the
+//     column stays in registers);
+//   panel role: RP = RPT*TW/4 rows per thread (at least 1) over the block's
+//     256 threads, panel width BWM = elements-per-thread budget / RP.
 struct Shape {
-  int tw, rpt, rp, bw;
+  int tw, rpt, rp;
 };
 Shape choose_shape(int m, int prec) {
-  Shape s;
   const int rpt_max = prec == 2 ? 16 : 8;
+  Shape s;
   s.tw = pow2_at_least(ceil_div(m, 64 * rpt_max));
-  s.rpt = ceil_div(m, 64 * s.tw);
-  s.rp = pow2_at_least(ceil_div(m, WG));
-  const int budget = prec == 2 ? 8 : 4, bwmax = prec == 2 ? 8 : 4;
-  s.bw = budget / s.rp < bwmax ? budget / s.rp : bwmax;
-  if (s.bw < 1) s.bw = 1;
+  s.rpt = pow2_at_least(ceil_div(m, 64 * s.tw));
+  s.rp = s.rpt * s.tw / NWAVE > 1 ? s.rpt * s.tw / NWAVE : 1;
   return s;
 }
+constexpr int bw_for(int L, int RP) {
+  // complex elements per thread held by the panel role: dd 8, qd 4; the
+  // panel width is capped (dd 4, qd 2) so that its loops unroll fully and
+  // every register array keeps static indices.
+  return L == 2 ? (8 / RP >= 4 ? 4 : (8 / RP >= 1 ? 8 / RP : 1)) : (4 / RP >= 2 ? 2 : (4 / RP >= 1 ? 4 / RP : 1));
+}
 
-template <class P, int RPT, int RP, int BWM>
+// LDS budget for staged q vectors (gfx950: 160 KiB per CU).
+constexpr size_t QSTAGE_BYTES = 128 * 1024;
+
+template <class P, int RPT, int TW>
 int launch_steps(StepArgs a, hipStream_t st) {
-  const int teams = NWAVE / a.tw;
+  constexpr int RP = RPT * TW / NWAVE > 1 ? RPT * TW / NWAVE : 1;
+  constexpr int BWM = bw_for(P::L, RP);
+  constexpr int TEAMS = NWAVE / TW;
+  a.bw = BWM;
+  a.npanel = ceil_div(a.n, a.bw);
+  a.mpad = RPT * 64 * TW > RP * WG ? RPT * 64 * TW : RP * WG;
+  const size_t qbytes = sizeof(double) * 2 * P::L * (size_t)a.mpad;
+  a.qstage = (int)(QSTAGE_BYTES / qbytes);
+  if (a.qstage > a.bw) a.qstage = a.bw;
+  if (a.qstage < 1) return MGS_ERR_DIMS;
+  const size_t shmem = qbytes * a.qstage;
+  auto kern = mgs_step_kernel<P, RPT, TW, RP, BWM>;
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)shmem) != hipSuccess)
+    return MGS_ERR_LAUNCH;
   const int last = a.ncols > a.n ? a.npanel : a.npanel - 1;
   for (int t = 0; t <= last; ++t) {
     a.t = t;
     const int jstart = (t + 1) * a.bw < a.n ? (t + 1) * a.bw : a.n;
     const int ntrail = t >= 1 ? a.ncols - jstart : 0;
-    const int tblocks = ntrail > 0 ? ceil_div(ntrail, teams) : 0;
+    const int tblocks = ntrail > 0 ? ceil_div(ntrail, TEAMS) : 0;
     const int grid = (t < a.npanel ? 1 : 0) + tblocks;
     if (grid == 0) continue;
-    hipLaunchKernelGGL((mgs_step_kernel<P, RPT, RP, BWM>), dim3(grid), dim3(WG), 0, st, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), shmem, st, a);
     if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
   }
   return MGS_OK;
 }
 
-template <class P, int RPT>
-int dispatch_rp(const StepArgs &a, int rp, hipStream_t st) {
-  constexpr int budget = P::L == 2 ? 8 : 4;
-  constexpr int bwmax = P::L == 2 ? 8 : 4;
-#define MGS_RP_CASE(R)                                                        \
-  case R: {                                                                   \
-    constexpr int bwm = (budget / R < bwmax ? budget / R : bwmax) > 0 ? (budget / R < bwmax ? budget / R : bwmax) : 1; \
-    return launch_steps<P, RPT, R, bwm>(a, st);                               \
-  }
-  switch (rp) {
-    MGS_RP_CASE(1)
-    MGS_RP_CASE(2)
-    MGS_RP_CASE(4)
-    MGS_RP_CASE(8)
-  }
+template <class P>
+int dispatch_shape(const StepArgs &a, const Shape &sh, hipStream_t st) {
   if constexpr (P::L == 2) {
-    if (rp == 16) return launch_steps<P, RPT, 16, 1>(a, st);
+    if (sh.tw == 1) {
+      switch (sh.rpt) {
+        case 1: return launch_steps<P, 1, 1>(a, st);
+        case 2: return launch_steps<P, 2, 1>(a, st);
+        case 4: return launch_steps<P, 4, 1>(a, st);
+        case 8: return launch_steps<P, 8, 1>(a, st);
+        case 16: return launch_steps<P, 16, 1>(a, st);
+      }
+    } else if (sh.rpt == 16 && sh.tw == 2) {
+      return launch_steps<P, 16, 2>(a, st);
+    } else if (sh.rpt == 16 && sh.tw == 4) {
+      return launch_steps<P, 16, 4>(a, st);
+    }
+  } else {
+    if (sh.tw == 1) {
+      switch (sh.rpt) {
+        case 1: return launch_steps<P, 1, 1>(a, st);
+        case 2: return launch_steps<P, 2, 1>(a, st);
+        case 4: return launch_steps<P, 4, 1>(a, st);
+        case 8: return launch_steps<P, 8, 1>(a, st);
+      }
+    } else if (sh.rpt == 8 && sh.tw == 2) {
+      return launch_steps<P, 8, 2>(a, st);
+    } else if (sh.rpt == 8 && sh.tw == 4) {
+      return launch_steps<P, 8, 4>(a, st);
+    }
   }
-#undef MGS_RP_CASE
   return MGS_ERR_DIMS;
 }
 
@@ -188,14 +220,10 @@ int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq,
   a.y = b ? y : nullptr;
   a.rho = b ? rho : nullptr;
   a.info = info;
-  a.bw = sh.bw;
   a.t = 0;
-  a.npanel = ceil_div(n, sh.bw);
-  a.rpt = sh.rpt;
-  a.tw = sh.tw;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (prec == 2) return dispatch_rp<PrecDD, 16>(a, sh.rp, st);
-  return dispatch_rp<PrecQD, 8>(a, sh.rp, st);
+  if (prec == 2) return dispatch_shape<PrecDD>(a, sh, st);
+  return dispatch_shape<PrecQD>(a, sh, st);
 }
 
 int ls_backsolve(int n, int prec, const double *R, int ldr, const double *y, double *x, int *info,
