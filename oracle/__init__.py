@@ -11,7 +11,9 @@ and quad-double arithmetic, of what the paper defines:
   the right-hand side (Section 3, Equation (1)),
 * column-oriented back substitution (Section 6, Figure 3),
 * least squares by sequential projections of b followed by back substitution,
-* the accuracy measure e of Section 4, Equation (2).
+* the accuracy measure e of Section 4, Equation (2),
+* the closed-form adjoint (dL/dA, dL/db) of the least-squares solution for
+  L = Re(g^H x) (the differentiation form; not in the paper).
 
 Array layout ("planar"): a complex matrix with ``cols`` columns and leading
 dimension ``ld`` in L-limb precision is a float64 array of shape
@@ -60,7 +62,8 @@ def lib():
         L.orc_ls_solve.argtypes = [I, I, I, P, I, P, I, P, P]
         L.orc_arith.argtypes = [I, I, I, P, P, P]
         L.orc_errors.argtypes = [I, I, I, P, I, P, I, P, I, P, I, P, I]
-        for f in (L.orc_mgs, L.orc_backsolve, L.orc_ls_solve, L.orc_arith, L.orc_errors):
+        L.orc_adjoint.argtypes = [I, I, I, P, I, P, P, P, P, P, I]
+        for f in (L.orc_mgs, L.orc_backsolve, L.orc_ls_solve, L.orc_arith, L.orc_errors, L.orc_adjoint):
             f.restype = I
         _lib = L
     return _lib
@@ -150,3 +153,20 @@ def errors(A, Q, R, cols=None, nthreads=0):
     lib().orc_errors(L, m, n, _p(A), m, _p(Q), m, _p(R), n, _p(cj), 0 if cj is None else len(cj),
                      _p(out), int(nthreads))
     return out
+
+
+def adjoint(A, b, g, nthreads=0):
+    """Closed-form adjoint of x = argmin ||b - A x|| for L = Re(g^H x).
+
+    Returns (gA (L,2,n,m), gb (L,2,m), x (L,2,n)), gradients in the
+    convention dL/dRe + i dL/dIm.
+    """
+    A, b, g = _c(A), _c(b), _c(g)
+    L, _, n, m = A.shape
+    gA = np.zeros_like(A)
+    gb = np.zeros((L, 2, m))
+    x = np.zeros((L, 2, n))
+    info = lib().orc_adjoint(L, m, n, _p(A), m, _p(b), _p(g), _p(gA), _p(gb), _p(x), int(nthreads))
+    if info != 0:
+        raise ValueError("orc_adjoint failed with %d" % info)
+    return gA, gb, x

@@ -11,6 +11,12 @@
 //   * Back substitution, Section 6, Figure 3: column oriented, for k = n..1:
 //     x_k = y_k / r_kk, then y_j -= r_jk x_k for j < k.
 //   * The accuracy measure of Section 4, Equation (2).
+//   * The adjoint of the least-squares solution (not in the paper; the
+//     differentiation form built around it): for L = Re(g^H x) with
+//     x = argmin ||b - A x||, full column rank, r = b - A x and
+//     z = (A^H A)^{-1} g, dL/db = A z and dL/dA = r z^H - (A z) x^H
+//     (gradient convention dL/dRe + i dL/dIm).  Evaluated from the MGS
+//     factors: w = R^{-H} g, z = R^{-1} w, A z = Q w.
 // Every reduction runs sequentially in ascending index order.  Only the loop
 // over independent trailing columns j is spread over OpenMP threads, so the
 // results are bitwise identical for every thread count.
@@ -155,6 +161,52 @@ int run_ls_solve(int m, int n, const double *Q, int ldq, const double *R, int ld
   CV<T> xv((size_t)n);
   backsolve<T>(n, Rv.data(), n, yv, xv.data());
   write_planar<T>(x, n, 1, n, xv);
+  return 0;
+}
+
+// Adjoint of the least-squares solution, closed form (see the header).
+template <class T>
+int run_adjoint(int m, int n, const double *A, int lda, const double *b, const double *gx, double *gA,
+                double *gb, double *xo, int nthreads) {
+  CV<T> W, A0, bv, gv;
+  read_planar<T>(A, m, n, lda, W);
+  A0 = W;
+  read_planar<T>(b, m, 1, m, bv);
+  read_planar<T>(gx, n, 1, n, gv);
+  W.insert(W.end(), bv.begin(), bv.end());
+  CV<T> Rv;
+  int info = mgs<T>(m, n, n + 1, W, Rv, nthreads);
+  if (info) return info;
+  // x = R^{-1} y, y the last column of the augmented R
+  CV<T> y(Rv.begin() + (size_t)n * n, Rv.begin() + (size_t)n * n + n);
+  CV<T> x((size_t)n), w((size_t)n), z((size_t)n);
+  backsolve<T>(n, Rv.data(), n, y, x.data());
+  // w = R^{-H} g: w_k = (g_k - sum_{j<k} conj(r_jk) w_j) / r_kk
+  for (int k = 0; k < n; ++k) {
+    C<T> s = gv[k];
+    for (int j = 0; j < k; ++j) s = csub(s, cmulc(Rv[(size_t)k * n + j], w[j]));
+    w[k] = cdivr(s, Rv[(size_t)k * n + k].re);
+  }
+  backsolve<T>(n, Rv.data(), n, w, z.data());
+  // bbar = Q w ; r = b - A x
+  CV<T> bbar((size_t)m), r((size_t)m);
+  for (int i = 0; i < m; ++i) {
+    C<T> s = czero<T>();
+    for (int k = 0; k < n; ++k) s = cadd(s, cmul(W[(size_t)k * m + i], w[k]));
+    bbar[i] = s;
+    C<T> t = bv[i];
+    for (int j = 0; j < n; ++j) t = csub(t, cmul(A0[(size_t)j * m + i], x[j]));
+    r[i] = t;
+  }
+  // Abar_ij = r_i conj(z_j) - bbar_i conj(x_j)
+  CV<T> G((size_t)m * n);
+  for (int j = 0; j < n; ++j) {
+    C<T> zc = {z[j].re, neg(z[j].im)}, xc = {x[j].re, neg(x[j].im)};
+    for (int i = 0; i < m; ++i) G[(size_t)j * m + i] = csub(cmul(r[i], zc), cmul(bbar[i], xc));
+  }
+  write_planar<T>(gA, m, n, m, G);
+  write_planar<T>(gb, m, 1, m, bbar);
+  if (xo) write_planar<T>(xo, n, 1, n, x);
   return 0;
 }
 
@@ -326,6 +378,20 @@ int orc_ls_solve(int prec, int m, int n, const double *Q, int ldq, const double 
     case 1: return run_ls_solve<double>(m, n, Q, ldq, R, ldr, b, x);
     case 2: return run_ls_solve<DD>(m, n, Q, ldq, R, ldr, b, x);
     case 4: return run_ls_solve<QD>(m, n, Q, ldq, R, ldr, b, x);
+  }
+  return -3;
+}
+
+// Adjoint of x = argmin ||b - A x|| for L = Re(g^H x): gA (m x n planar,
+// ld m), gb (m), and x (n, may be NULL).  Returns info of the MGS.
+int orc_adjoint(int prec, int m, int n, const double *A, int lda, const double *b, const double *gx,
+                double *gA, double *gb, double *x, int nthreads) {
+  if (n < 1 || m < n || lda < m) return -1;
+  int t = threads_or_default(nthreads);
+  switch (prec) {
+    case 1: return run_adjoint<double>(m, n, A, lda, b, gx, gA, gb, x, t);
+    case 2: return run_adjoint<DD>(m, n, A, lda, b, gx, gA, gb, x, t);
+    case 4: return run_adjoint<QD>(m, n, A, lda, b, gx, gA, gb, x, t);
   }
   return -3;
 }
