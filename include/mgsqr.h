@@ -59,7 +59,7 @@ enum {
   MGS_ERR_UNSUPPORTED = -6  /* unknown operation code */
 };
 
-enum { MGS_OP_QR = 0, MGS_OP_SOLVE = 1 };
+enum { MGS_OP_QR = 0, MGS_OP_SOLVE = 1, MGS_OP_ADJOINT = 2 };
 
 /* Largest supported row count m: dd 4096, qd 2048. */
 #define MGS_MAX_ROWS_DD 4096
@@ -69,7 +69,8 @@ int mgs_abi_version(void);
 const char *mgs_status_string(int status);
 
 /* Bytes of device workspace needed by operation `op` (MGS_OP_QR with a
- * right-hand side, MGS_OP_SOLVE) for an m x n problem; written to *bytes. */
+ * right-hand side, MGS_OP_SOLVE, MGS_OP_ADJOINT) for an m x n problem;
+ * written to *bytes. */
 int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
 
 /*
@@ -118,6 +119,25 @@ int ls_solve(int m, int n, int prec, const double *Q, int ldq, const double *R, 
  */
 int ls_backsolve(int n, int prec, const double *R, int ldr, const double *y, double *x, int *info,
                  mgs_stream_t stream);
+
+/*
+ * ls_adjoint -- gradients of a loss L(x) through the least-squares solution
+ * x = argmin ||b - A x|| (the differentiation form built around the solver
+ * of Section 3; not itself in the paper).  Given gx = dL/dRe(x) + i dL/dIm(x)
+ * and the MGS factors A = Q R of full column rank:
+ *   w = R^{-H} gx, z = R^{-1} w (so z = (A^H A)^{-1} gx),
+ *   gb = Q w (= A z),  r = b - A x,  gA = r z^H - gb x^H,
+ * gA and gb in the same convention (dL/dRe + i dL/dIm).
+ *   A [in] m x n (lda), b [in] m, Q [in] m x n (ldq), R [in] n x n (ldr),
+ *   x [in] n (the solution from the same factors), gx [in] n.
+ *   gA [out] m x n planar (ldga >= m), gb [out] m planar.
+ *   work: mgs_workspace_size(m, n, prec, MGS_OP_ADJOINT) bytes.
+ *   info: 0, or k > 0 when r_kk is zero or not finite.
+ * gA may not alias A or Q, gb may not alias b.
+ */
+int ls_adjoint(int m, int n, int prec, const double *A, int lda, const double *b, const double *Q, int ldq,
+               const double *R, int ldr, const double *x, const double *gx, double *gA, int ldga, double *gb,
+               void *work, size_t work_bytes, int *info, mgs_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -13,10 +13,11 @@ SO_PATH = os.path.join(HERE, "libmgsqr.so")
 MGS_OK = 0
 MGS_OP_QR = 0
 MGS_OP_SOLVE = 1
+MGS_OP_ADJOINT = 2
 MGS_MAX_ROWS = {2: 4096, 4: 2048}
 
 EXPORTS = ("mgs_abi_version", "mgs_status_string", "mgs_workspace_size", "mgs_qr", "ls_solve",
-           "ls_backsolve")
+           "ls_backsolve", "ls_adjoint")
 
 _lib = None
 
@@ -48,6 +49,8 @@ def lib():
         L.ls_solve.restype = I
         L.ls_backsolve.argtypes = [I, I, P, I, P, P, P, P]
         L.ls_backsolve.restype = I
+        L.ls_adjoint.argtypes = [I, I, I, P, I, P, P, I, P, I, P, P, P, I, P, P, S, P, P]
+        L.ls_adjoint.restype = I
         _lib = L
     return _lib
 

@@ -101,3 +101,50 @@ def lstsq(A, b):
     f["x"] = x
     f["info_backsolve"] = info2
     return f
+
+
+def ls_adjoint(A, b, Q, R, x, gx, *, gA=None, gb=None, info=None, work=None):
+    """Gradients (gA, gb) of a loss through x = argmin ||b - A x||.
+
+    gx = dL/dRe(x) + i dL/dIm(x) (planar [prec, 2, n]); returns gA, gb in the
+    same convention, from the saved MGS factors Q, R (full column rank).
+    """
+    _check_planar("A", A, ndim=4)
+    prec, _, n, m = A.shape
+    for name, t, nd in (("b", b, 3), ("Q", Q, 4), ("R", R, 4), ("x", x, 3), ("gx", gx, 3)):
+        _check_planar(name, t, prec, nd)
+    dev = A.device
+    gA = torch.empty_like(A) if gA is None else gA
+    gb = torch.empty_like(b) if gb is None else gb
+    info = torch.empty(1, dtype=torch.int32, device=dev) if info is None else info
+    work = workspace(m, n, prec, _lib.MGS_OP_ADJOINT, dev) if work is None else work
+    st = _lib.lib().ls_adjoint(m, n, prec, _ptr(A), m, _ptr(b), _ptr(Q), m, _ptr(R), R.shape[3], _ptr(x),
+                               _ptr(gx), _ptr(gA), m, _ptr(gb), _ptr(work), work.numel() * 8, _ptr(info),
+                               _stream(A))
+    _lib.check("ls_adjoint", st)
+    return gA, gb, info
+
+
+class LstsqFn(torch.autograd.Function):
+    """x = argmin ||b - A x|| by MGS on [A b] and back substitution, with the
+    hand-written adjoint as its backward.
+
+    Tensors are planar dd / qd ([prec, 2, ...] float64 on the GPU); the
+    gradients returned are extended-precision VALUES in the same layout (the
+    limb planes encode one number per entry, they are not per-limb partial
+    derivatives), in the convention dL/dRe + i dL/dIm.
+    """
+
+    @staticmethod
+    def forward(ctx, A, b):
+        f = mgs_qr(A.detach(), b.detach())
+        x, _ = ls_backsolve(f["R"], f["y"])
+        ctx.save_for_backward(A.detach(), b.detach(), f["Q"], f["R"], x)
+        ctx.info = (f["info"],)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        A, b, Q, R, x = ctx.saved_tensors
+        gA, gb, _ = ls_adjoint(A, b, Q, R, x, gx.contiguous())
+        return gA, gb

@@ -259,6 +259,38 @@ struct PrecDD {
     c = __fma_rn(-q.im.l, a.re.h, c);
     acc.ci = c + ((e1 + e2) + (t1 + t2));
   }
+  // acc += a * b (no conjugation): re a.re b.re - a.im b.im, im a.re b.im + a.im b.re
+  __device__ static __forceinline__ void acc_cmul(Acc &acc, const C &a, const C &b) {
+    double p1, e1, p2, e2, t1, t2;
+    two_prod(a.re.h, b.re.h, p1, e1);
+    two_prod(-a.im.h, b.im.h, p2, e2);
+    two_sum(acc.sr, p1, acc.sr, t1);
+    two_sum(acc.sr, p2, acc.sr, t2);
+    double c = acc.cr;
+    c = __fma_rn(a.re.h, b.re.l, c);
+    c = __fma_rn(a.re.l, b.re.h, c);
+    c = __fma_rn(-a.im.h, b.im.l, c);
+    c = __fma_rn(-a.im.l, b.im.h, c);
+    acc.cr = c + ((e1 + e2) + (t1 + t2));
+    two_prod(a.re.h, b.im.h, p1, e1);
+    two_prod(a.im.h, b.re.h, p2, e2);
+    two_sum(acc.si, p1, acc.si, t1);
+    two_sum(acc.si, p2, acc.si, t2);
+    c = acc.ci;
+    c = __fma_rn(a.re.h, b.im.l, c);
+    c = __fma_rn(a.re.l, b.im.h, c);
+    c = __fma_rn(a.im.h, b.re.l, c);
+    c = __fma_rn(a.im.l, b.re.h, c);
+    acc.ci = c + ((e1 + e2) + (t1 + t2));
+  }
+  __device__ static __forceinline__ void acc_set(Acc &acc, const C &v) {
+    acc.sr = v.re.h;
+    acc.cr = v.re.l;
+    acc.si = v.im.h;
+    acc.ci = v.im.l;
+  }
+  __device__ static __forceinline__ C conj(const C &v) { return {v.re, {-v.im.h, -v.im.l}}; }
+  __device__ static __forceinline__ C cneg(const C &v) { return {{-v.re.h, -v.re.l}, {-v.im.h, -v.im.l}}; }
   // acc.re += |a|^2
   __device__ static __forceinline__ void acc_abs2(Acc &acc, const C &a) {
     double p1, e1, p2, e2, t1, t2;
@@ -391,6 +423,13 @@ struct PrecQD {
   __device__ static __forceinline__ void acc_abs2(Acc &acc, const C &a) {
     acc.re = qd_add(acc.re, qd_add(qd_mul(a.re, a.re), qd_mul(a.im, a.im)));
   }
+  __device__ static __forceinline__ void acc_cmul(Acc &acc, const C &a, const C &b) {
+    acc.re = qd_add(acc.re, qd_sub(qd_mul(a.re, b.re), qd_mul(a.im, b.im)));
+    acc.im = qd_add(acc.im, qd_add(qd_mul(a.re, b.im), qd_mul(a.im, b.re)));
+  }
+  __device__ static __forceinline__ void acc_set(Acc &acc, const C &v) { acc = v; }
+  __device__ static __forceinline__ C conj(const C &v) { return {v.re, qd_neg(v.im)}; }
+  __device__ static __forceinline__ C cneg(const C &v) { return {qd_neg(v.re), qd_neg(v.im)}; }
   __device__ static __forceinline__ void acc_merge(Acc &a, const Acc &b) {
     a.re = qd_add(a.re, b.re);
     a.im = qd_add(a.im, b.im);

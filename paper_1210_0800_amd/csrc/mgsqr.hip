@@ -7,6 +7,7 @@
 
 #include <cstdint>
 
+#include "adjoint_kernels.hpp"
 #include "mgs_kernels.hpp"
 
 using namespace mgsq;
@@ -158,6 +159,50 @@ int project_launch(int m, int n, const double *Q, int ldq, const double *b, doub
 
 size_t qr_work_bytes(int m, int prec) { return round256(sizeof(double) * 2 * (size_t)prec * m); }
 size_t solve_work_bytes(int n, int prec) { return round256(sizeof(double) * 2 * (size_t)prec * n); }
+// adjoint: w (n), z (n), r (m)
+size_t adjoint_work_bytes(int m, int n, int prec) {
+  return 2 * round256(sizeof(double) * 2 * (size_t)prec * n) + round256(sizeof(double) * 2 * (size_t)prec * m);
+}
+
+template <class P>
+int fwdsub_launch(int n, const double *R, int ldr, const double *g, double *w, int *info, hipStream_t st) {
+  const int ny = pow2_at_least(ceil_div(n, WG));
+  const size_t planeR = (size_t)ldr * n;
+#define MGS_FS_CASE(NYV)                                                                                 \
+  case NYV:                                                                                              \
+    hipLaunchKernelGGL((fwdsub_kernel<P, NYV>), dim3(1), dim3(WG), 0, st, n, R, ldr, planeR, g, w, info); \
+    break;
+  switch (ny) {
+    MGS_FS_CASE(1)
+    MGS_FS_CASE(2)
+    MGS_FS_CASE(4)
+    MGS_FS_CASE(8)
+    MGS_FS_CASE(16)
+    default:
+      return MGS_ERR_DIMS;
+  }
+#undef MGS_FS_CASE
+  return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
+}
+
+template <class P>
+int adjoint_launch(int m, int n, const double *A, int lda, const double *b, const double *Q, int ldq,
+                   const double *R, int ldr, const double *x, const double *gx, double *gA, int ldga, double *gb,
+                   void *work, int *info, hipStream_t st) {
+  double *w = static_cast<double *>(work);
+  double *z = w + round256(sizeof(double) * 2 * P::L * (size_t)n) / sizeof(double);
+  double *r = z + round256(sizeof(double) * 2 * P::L * (size_t)n) / sizeof(double);
+  int rc = fwdsub_launch<P>(n, R, ldr, gx, w, info, st);
+  if (rc != MGS_OK) return rc;
+  rc = backsolve_launch<P>(n, R, ldr, w, z, info, st);
+  if (rc != MGS_OK) return rc;
+  hipLaunchKernelGGL((adj_gemv_kernel<P>), dim3(ceil_div(m, WG)), dim3(WG), 0, st, m, n, Q, ldq, (size_t)ldq * n,
+                     A, lda, (size_t)lda * n, b, x, w, gb, r);
+  if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
+  hipLaunchKernelGGL((adj_rank2_kernel<P>), dim3(ceil_div(m, WG), n), dim3(WG), 0, st, m, n, r, z, gb, x, gA, ldga,
+                     (size_t)ldga * n);
+  return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
+}
 
 }  // namespace
 
@@ -185,6 +230,7 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes) {
   switch (op) {
     case MGS_OP_QR: *bytes = qr_work_bytes(m, prec); return MGS_OK;
     case MGS_OP_SOLVE: *bytes = solve_work_bytes(n, prec); return MGS_OK;
+    case MGS_OP_ADJOINT: *bytes = adjoint_work_bytes(m, n, prec); return MGS_OK;
   }
   return MGS_ERR_UNSUPPORTED;
 }
@@ -251,6 +297,21 @@ int ls_solve(int m, int n, int prec, const double *Q, int ldq, const double *R, 
   if (rc != MGS_OK) return rc;
   if (prec == 2) return backsolve_launch<PrecDD>(n, R, ldr, y, x, info, st);
   return backsolve_launch<PrecQD>(n, R, ldr, y, x, info, st);
+}
+
+int ls_adjoint(int m, int n, int prec, const double *A, int lda, const double *b, const double *Q, int ldq,
+               const double *R, int ldr, const double *x, const double *gx, double *gA, int ldga, double *gb,
+               void *work, size_t work_bytes, int *info, mgs_stream_t stream) {
+  if (prec != 2 && prec != 4) return MGS_ERR_PREC;
+  if (n < 1 || m < n || m > max_rows(prec) || lda < m || ldq < m || ldr < n || ldga < m) return MGS_ERR_DIMS;
+  if (!aligned8(A) || !aligned8(b) || !aligned8(Q) || !aligned8(R) || !aligned8(x) || !aligned8(gx) ||
+      !aligned8(gA) || !aligned8(gb) || !aligned8(work) || !aligned8(info))
+    return MGS_ERR_POINTER;
+  if (gA == A || gA == Q || gb == b) return MGS_ERR_POINTER;
+  if (work_bytes < adjoint_work_bytes(m, n, prec)) return MGS_ERR_WORKSPACE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (prec == 2) return adjoint_launch<PrecDD>(m, n, A, lda, b, Q, ldq, R, ldr, x, gx, gA, ldga, gb, work, info, st);
+  return adjoint_launch<PrecQD>(m, n, A, lda, b, Q, ldq, R, ldr, x, gx, gA, ldga, gb, work, info, st);
 }
 
 }  // extern "C"

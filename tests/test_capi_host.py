@@ -109,3 +109,24 @@ def test_binding_refuses_cpu_tensors():
     A = torch.zeros(2, 2, 3, 4, dtype=torch.float64)
     with pytest.raises(ValueError):
         api.mgs_qr(A)
+
+
+def test_ls_adjoint_rejects_bad_arguments():
+    L = _lib.lib()
+    args = [8, 4, 2, FAKE, 8, FAKE + 64, FAKE + 128, 8, FAKE + 192, 4, FAKE + 256, FAKE + 320, FAKE + 384, 8,
+            FAKE + 448, FAKE + 512, 1 << 20, FAKE + 576, None]
+    def call(**kw):
+        a = list(args)
+        names = ["m", "n", "prec", "A", "lda", "b", "Q", "ldq", "R", "ldr", "x", "gx", "gA", "ldga", "gb", "work",
+                 "wb", "info", "stream"]
+        for k, v in kw.items():
+            a[names.index(k)] = v
+        return L.ls_adjoint(*a)
+    assert call(prec=3) == -3
+    assert call(m=3) == -1
+    assert call(ldga=7) == -1
+    assert call(gA=None) == -2
+    assert call(gA=FAKE) == -2        # aliases A
+    assert call(gb=FAKE + 64) == -2   # aliases b
+    assert call(wb=16) == -4
+    assert _lib.workspace_size(8, 4, 2, _lib.MGS_OP_ADJOINT) == 3 * 256
