@@ -59,7 +59,7 @@ enum {
   MGS_ERR_UNSUPPORTED = -6  /* unknown operation code */
 };
 
-enum { MGS_OP_QR = 0, MGS_OP_SOLVE = 1, MGS_OP_ADJOINT = 2 };
+enum { MGS_OP_QR = 0, MGS_OP_SOLVE = 1, MGS_OP_ADJOINT = 2, MGS_OP_REFINE = 3 };
 
 /* Largest supported row count m: dd 4096, qd 2048. */
 #define MGS_MAX_ROWS_DD 4096
@@ -69,7 +69,8 @@ int mgs_abi_version(void);
 const char *mgs_status_string(int status);
 
 /* Bytes of device workspace needed by operation `op` (MGS_OP_QR with a
- * right-hand side, MGS_OP_SOLVE, MGS_OP_ADJOINT) for an m x n problem;
+ * right-hand side, MGS_OP_SOLVE, MGS_OP_ADJOINT, MGS_OP_REFINE) for an
+ * m x n problem;
  * written to *bytes. */
 int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
 
@@ -138,6 +139,36 @@ int ls_backsolve(int n, int prec, const double *R, int ldr, const double *y, dou
 int ls_adjoint(int m, int n, int prec, const double *A, int lda, const double *b, const double *Q, int ldq,
                const double *R, int ldr, const double *x, const double *gx, double *gA, int ldga, double *gb,
                void *work, size_t work_bytes, int *info, mgs_stream_t stream);
+
+/*
+ * mgs_refine_solve -- the precision form (not in the paper; built around
+ * the solver of Section 3): least squares A x = b with a factorisation in
+ * plain FP64 and the solution refined in dd / qd.
+ *   1. [fl64(A) fl64(b)] is factored by blocked MGS in FP64: panels of
+ *      `block` = 64 columns, each factored by MGS (Figure 1), the trailing
+ *      products W = Q_p^H A_t and A_t -= Q_p W on FP64 matrix cores; b is
+ *      the last column, so y = Q^H b keeps the augmented semantics of
+ *      Equation (1).  x0 = R^{-1} y in FP64.
+ *   2. Repeat up to max_iter times: r = b - A x in dd / qd (A, b, x in the
+ *      working precision), d = FP64 solve of fl64(r) (the same panel
+ *      projections replayed on r, then R^{-1}), x += d in dd / qd; stop when
+ *      ||d|| <= tol ||x||, or when ||d|| > ||d_prev|| / 2 (the corrections
+ *      stalled; that d is not applied): converged to the attainable accuracy
+ *      if the last applied ||d|| / ||x|| <= sqrt(tol), stagnation otherwise.
+ *   A [in] m x n planar (lda), b [in] m planar, x [out] n planar, all in
+ *   `prec` limbs.  block must be 64.  tol >= 0 (e.g. 2^-104 dd, 2^-209 qd).
+ *   iters [out, device int or NULL]: refinement steps applied.
+ *   err_est [out, device double or NULL]: ||d|| / ||x|| of the last step.
+ *   work: mgs_workspace_size(m, n, prec, MGS_OP_REFINE) bytes.
+ *   info [device int]: 0 converged; k > 0 zero or non-finite norm at column
+ *   k of the FP64 factorisation; -1 stagnated above sqrt(tol); -2 max_iter
+ *   reached first.
+ * Convergence needs kappa(A) * 2^-53 well below 1 and a consistent or
+ * nearly consistent system.
+ */
+int mgs_refine_solve(int m, int n, int prec, const double *A, int lda, const double *b, double *x, int block,
+                     double tol, int max_iter, int *iters, double *err_est, void *work, size_t work_bytes, int *info,
+                     mgs_stream_t stream);
 
 #ifdef __cplusplus
 }

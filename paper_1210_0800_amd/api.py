@@ -125,6 +125,30 @@ def ls_adjoint(A, b, Q, R, x, gx, *, gA=None, gb=None, info=None, work=None):
     return gA, gb, info
 
 
+def refine_lstsq(A, b, *, tol=None, max_iter=20, x=None, work=None):
+    """Precision form: FP64 blocked-MGS factorisation (panels of 64, trailing
+    products on matrix cores) and dd / qd iterative refinement of x.
+
+    Returns dict(x, iters, err_est, info) of device tensors; info 0 converged,
+    k > 0 bad column k, -1 stagnated, -2 max_iter reached.
+    """
+    _check_planar("A", A, ndim=4)
+    prec, _, n, m = A.shape
+    _check_planar("b", b, prec, 3)
+    dev = A.device
+    if tol is None:
+        tol = 2.0 ** -104 if prec == 2 else 2.0 ** -209
+    x = torch.empty((prec, 2, n), dtype=torch.float64, device=dev) if x is None else x
+    iters = torch.zeros(1, dtype=torch.int32, device=dev)
+    err = torch.zeros(1, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    work = workspace(m, n, prec, _lib.MGS_OP_REFINE, dev) if work is None else work
+    st = _lib.lib().mgs_refine_solve(m, n, prec, _ptr(A), m, _ptr(b), _ptr(x), 64, float(tol), int(max_iter),
+                                     _ptr(iters), _ptr(err), _ptr(work), work.numel() * 8, _ptr(info), _stream(A))
+    _lib.check("mgs_refine_solve", st)
+    return dict(x=x, iters=iters, err_est=err, info=info)
+
+
 class LstsqFn(torch.autograd.Function):
     """x = argmin ||b - A x|| by MGS on [A b] and back substitution, with the
     hand-written adjoint as its backward.

@@ -290,6 +290,11 @@ struct PrecDD {
     acc.ci = v.im.l;
   }
   __device__ static __forceinline__ C conj(const C &v) { return {v.re, {-v.im.h, -v.im.l}}; }
+  // v += (dr + i di) for FP64 dr, di
+  __device__ static __forceinline__ void add_cd(C &v, double dr, double di) {
+    v.re = dd_add(v.re, {dr, 0.0});
+    v.im = dd_add(v.im, {di, 0.0});
+  }
   __device__ static __forceinline__ C cneg(const C &v) { return {{-v.re.h, -v.re.l}, {-v.im.h, -v.im.l}}; }
   // acc.re += |a|^2
   __device__ static __forceinline__ void acc_abs2(Acc &acc, const C &a) {
@@ -429,6 +434,10 @@ struct PrecQD {
   }
   __device__ static __forceinline__ void acc_set(Acc &acc, const C &v) { acc = v; }
   __device__ static __forceinline__ C conj(const C &v) { return {v.re, qd_neg(v.im)}; }
+  __device__ static __forceinline__ void add_cd(C &v, double dr, double di) {
+    v.re = qd_add(v.re, qd_from(dr));
+    v.im = qd_add(v.im, qd_from(di));
+  }
   __device__ static __forceinline__ C cneg(const C &v) { return {qd_neg(v.re), qd_neg(v.im)}; }
   __device__ static __forceinline__ void acc_merge(Acc &a, const Acc &b) {
     a.re = qd_add(a.re, b.re);
@@ -465,6 +474,73 @@ struct PrecQD {
     p[2 * stride] = v.x2;
     p[3 * stride] = v.x3;
   }
+};
+
+// Plain complex double (FP64), for the blocked factorisation of the
+// precision form: ordinary rounding, FMA where the product is fused.
+struct cd {
+  double re, im;
+};
+struct PrecD {
+  static constexpr int L = 1;
+  using R = double;
+  using C = cd;
+  struct Acc {
+    double re, im;
+  };
+  __device__ static __forceinline__ C load(const double *p, size_t plane) { return {p[0], p[plane]}; }
+  __device__ static __forceinline__ void store(double *p, size_t plane, const C &v) {
+    p[0] = v.re;
+    p[plane] = v.im;
+  }
+  __device__ static __forceinline__ C czero() { return {0.0, 0.0}; }
+  __device__ static __forceinline__ R rzero() { return 0.0; }
+  __device__ static __forceinline__ void acc_zero(Acc &a) { a.re = a.im = 0.0; }
+  __device__ static __forceinline__ void acc_cmulc(Acc &acc, const C &q, const C &a) {
+    acc.re = __fma_rn(q.re, a.re, acc.re);
+    acc.re = __fma_rn(q.im, a.im, acc.re);
+    acc.im = __fma_rn(q.re, a.im, acc.im);
+    acc.im = __fma_rn(-q.im, a.re, acc.im);
+  }
+  __device__ static __forceinline__ void acc_cmul(Acc &acc, const C &a, const C &b) {
+    acc.re = __fma_rn(a.re, b.re, acc.re);
+    acc.re = __fma_rn(-a.im, b.im, acc.re);
+    acc.im = __fma_rn(a.re, b.im, acc.im);
+    acc.im = __fma_rn(a.im, b.re, acc.im);
+  }
+  __device__ static __forceinline__ void acc_abs2(Acc &acc, const C &a) {
+    acc.re = __fma_rn(a.re, a.re, acc.re);
+    acc.re = __fma_rn(a.im, a.im, acc.re);
+  }
+  __device__ static __forceinline__ void acc_set(Acc &acc, const C &v) {
+    acc.re = v.re;
+    acc.im = v.im;
+  }
+  __device__ static __forceinline__ void acc_merge(Acc &a, const Acc &b) {
+    a.re += b.re;
+    a.im += b.im;
+  }
+  __device__ static __forceinline__ void acc_merge_re(Acc &a, const Acc &b) { a.re += b.re; }
+  __device__ static __forceinline__ Acc acc_shfl_xor(const Acc &a, int mask) {
+    return {__shfl_xor(a.re, mask), __shfl_xor(a.im, mask)};
+  }
+  __device__ static __forceinline__ Acc acc_shfl_xor_re(const Acc &a, int mask) { return {__shfl_xor(a.re, mask), 0.0}; }
+  __device__ static __forceinline__ C acc_value(const Acc &a) { return {a.re, a.im}; }
+  __device__ static __forceinline__ R acc_value_re(const Acc &a) { return a.re; }
+  __device__ static __forceinline__ C conj(const C &v) { return {v.re, -v.im}; }
+  __device__ static __forceinline__ C cneg(const C &v) { return {-v.re, -v.im}; }
+  // a -= r q
+  __device__ static __forceinline__ void upd(C &a, const C &r, const C &q) {
+    a.re = __fma_rn(-r.re, q.re, a.re);
+    a.re = __fma_rn(r.im, q.im, a.re);
+    a.im = __fma_rn(-r.re, q.im, a.im);
+    a.im = __fma_rn(-r.im, q.re, a.im);
+  }
+  __device__ static __forceinline__ C scale(const C &a, const R &s) { return {a.re * s, a.im * s}; }
+  __device__ static __forceinline__ R sqrt_(const R &s) { return sqrt(s); }
+  __device__ static __forceinline__ R recip(const R &s) { return 1.0 / s; }
+  __device__ static __forceinline__ bool ok_norm(const R &s) { return s > 0.0 && s < INFINITY; }
+  __device__ static __forceinline__ void store_real(double *p, size_t stride, const R &v) { p[0] = v; }
 };
 
 }  // namespace mgsq

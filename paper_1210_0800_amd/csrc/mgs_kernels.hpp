@@ -71,6 +71,8 @@ struct StepArgs {
   int bw, t, npanel;
   int mpad;    // rows padded to the launch shape: LDS plane stride, multiple of WG
   int qstage;  // q vectors staged in LDS at a time
+  int kbase;   // column offset of this matrix in the caller's, for info
+  int init_info;  // the first launch clears *info
 };
 
 // Copy q_k0 .. q_{k0+cnt-1} from Q into LDS, layout [vector][plane][row]
@@ -189,7 +191,7 @@ __device__ void panel_role(const StepArgs &a, typename P::Acc *lds, double *qs) 
   const int k0 = a.t * a.bw;
   const int nb = min(a.bw, a.n - k0);
   const bool first = a.t <= 1;
-  if (a.t == 0 && tid == 0) *a.info = 0;
+  if (a.t == 0 && tid == 0 && a.init_info) *a.info = 0;
 
   C col[BWM][RP];
 #pragma unroll
@@ -260,7 +262,7 @@ __device__ void panel_role(const StepArgs &a, typename P::Acc *lds, double *qs) 
       for (int w = 1; w < NWAVE; ++w) P::acc_merge_re(s, lds[w * BWM + c]);
       lds_barrier();
       typename P::R s2 = P::acc_value_re(s);
-      if (!P::ok_norm(s2) && tid == 0 && *a.info == 0) *a.info = k + 1;
+      if (!P::ok_norm(s2) && tid == 0 && *a.info == 0) *a.info = a.kbase + k + 1;
       typename P::R rkk = P::sqrt_(s2);
       typename P::R inv = P::recip(rkk);
       size_t pq;
@@ -423,7 +425,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 // LDS broadcast (double-buffered: one barrier per step) and one update.
 template <class P, int NY>
 __global__ __launch_bounds__(WG) void backsolve_kernel(int n, const double *R, int ldr, size_t planeR,
-                                                        const double *y, double *x, int *info) {
+                                                        const double *y, size_t planeY, double *x, int *info,
+                                                        const int *skip) {
+  if (skip != nullptr && *skip != 0) return;
   using C = typename P::C;
   using Rl = typename P::R;
   __shared__ C xs[2];
@@ -437,7 +441,7 @@ __global__ __launch_bounds__(WG) void backsolve_kernel(int n, const double *R, i
   for (int s = 0; s < NY; ++s) {
     int j = s * WG + tid;
     if (j < n) {
-      yv[s] = P::load(y + j, (size_t)n);
+      yv[s] = P::load(y + j, planeY);
       C d = P::load(R + (size_t)j * ldr + j, planeR);
       if (!P::ok_norm(d.re)) atomicMin(&bad, j + 1);
       inv[s] = P::recip(d.re);
@@ -447,7 +451,7 @@ __global__ __launch_bounds__(WG) void backsolve_kernel(int n, const double *R, i
     }
   }
   __syncthreads();
-  if (tid == 0) *info = (bad == 0x7fffffff) ? 0 : bad;
+  if (tid == 0 && info != nullptr) *info = (bad == 0x7fffffff) ? 0 : bad;
 #pragma unroll 1
   for (int k = n - 1; k >= 0; --k) {
     const int sk = k / WG, owner = k - sk * WG;

@@ -9,6 +9,7 @@
 
 #include "adjoint_kernels.hpp"
 #include "mgs_kernels.hpp"
+#include "precision_kernels.hpp"
 
 using namespace mgsq;
 
@@ -34,7 +35,7 @@ struct Shape {
   int tw, rpt, rp;
 };
 Shape choose_shape(int m, int prec) {
-  const int rpt_max = prec == 2 ? 16 : 8;
+  const int rpt_max = prec == 1 ? 32 : (prec == 2 ? 16 : 8);
   Shape s;
   s.tw = pow2_at_least(ceil_div(m, 64 * rpt_max));
   s.rpt = pow2_at_least(ceil_div(m, 64 * s.tw));
@@ -42,10 +43,12 @@ Shape choose_shape(int m, int prec) {
   return s;
 }
 constexpr int bw_for(int L, int RP) {
-  // complex elements per thread held by the panel role: dd 8, qd 4; the
-  // panel width is capped (dd 4, qd 2) so that its loops unroll fully and
-  // every register array keeps static indices.
-  return L == 2 ? (8 / RP >= 4 ? 4 : (8 / RP >= 1 ? 8 / RP : 1)) : (4 / RP >= 2 ? 2 : (4 / RP >= 1 ? 4 / RP : 1));
+  // complex elements per thread held by the panel role: FP64 16, dd 8,
+  // qd 4; the panel width is capped (FP64 / dd 4, qd 2) so that its loops
+  // unroll fully and every register array keeps static indices.
+  return L == 1 ? (16 / RP >= 4 ? 4 : (16 / RP >= 1 ? 16 / RP : 1))
+                : L == 2 ? (8 / RP >= 4 ? 4 : (8 / RP >= 1 ? 8 / RP : 1))
+                         : (4 / RP >= 2 ? 2 : (4 / RP >= 1 ? 4 / RP : 1));
 }
 
 // LDS budget for staged q vectors (gfx950: 160 KiB per CU).
@@ -84,7 +87,20 @@ int launch_steps(StepArgs a, hipStream_t st) {
 
 template <class P>
 int dispatch_shape(const StepArgs &a, const Shape &sh, hipStream_t st) {
-  if constexpr (P::L == 2) {
+  if constexpr (P::L == 1) {
+    if (sh.tw == 1) {
+      switch (sh.rpt) {
+        case 1: return launch_steps<P, 1, 1>(a, st);
+        case 2: return launch_steps<P, 2, 1>(a, st);
+        case 4: return launch_steps<P, 4, 1>(a, st);
+        case 8: return launch_steps<P, 8, 1>(a, st);
+        case 16: return launch_steps<P, 16, 1>(a, st);
+        case 32: return launch_steps<P, 32, 1>(a, st);
+      }
+    } else if (sh.rpt == 32 && sh.tw == 2) {
+      return launch_steps<P, 32, 2>(a, st);
+    }
+  } else if constexpr (P::L == 2) {
     if (sh.tw == 1) {
       switch (sh.rpt) {
         case 1: return launch_steps<P, 1, 1>(a, st);
@@ -116,12 +132,15 @@ int dispatch_shape(const StepArgs &a, const Shape &sh, hipStream_t st) {
 }
 
 template <class P>
-int backsolve_launch(int n, const double *R, int ldr, const double *y, double *x, int *info, hipStream_t st) {
+int backsolve_launch(int n, const double *R, int ldr, const double *y, double *x, int *info, hipStream_t st,
+                     size_t planeR = 0, const int *skip = nullptr, size_t planeY = 0) {
   const int ny = pow2_at_least(ceil_div(n, WG));
-  const size_t planeR = (size_t)ldr * n;
-#define MGS_NY_CASE(NYV)                                                                                  \
-  case NYV:                                                                                               \
-    hipLaunchKernelGGL((backsolve_kernel<P, NYV>), dim3(1), dim3(WG), 0, st, n, R, ldr, planeR, y, x, info); \
+  if (planeR == 0) planeR = (size_t)ldr * n;
+  if (planeY == 0) planeY = (size_t)n;
+#define MGS_NY_CASE(NYV)                                                                                    \
+  case NYV:                                                                                                 \
+    hipLaunchKernelGGL((backsolve_kernel<P, NYV>), dim3(1), dim3(WG), 0, st, n, R, ldr, planeR, y, planeY,    \
+                       x, info, skip);                                                                      \
     break;
   switch (ny) {
     MGS_NY_CASE(1)
@@ -204,6 +223,119 @@ int adjoint_launch(int m, int n, const double *A, int lda, const double *b, cons
   return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
 }
 
+// ------------------------------------------------------ precision form --
+struct RefineWork {
+  double *Q64, *R64, *y64, *d64, *r64;
+  void *partial;
+  RefineCtl *ctl;
+  size_t bytes;
+};
+RefineWork refine_layout(int m, int n, int prec, void *base) {
+  const int nchunk = ceil_div(n, NBP);
+  const size_t acc_bytes = prec == 2 ? 32 : 64;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off += round256(b);
+    return static_cast<char *>(base) + o;
+  };
+  RefineWork w;
+  w.Q64 = reinterpret_cast<double *>(take(sizeof(double) * 2 * (size_t)m * (n + 1)));
+  w.R64 = reinterpret_cast<double *>(take(sizeof(double) * 2 * (size_t)n * (n + 1)));
+  w.y64 = reinterpret_cast<double *>(take(sizeof(double) * 2 * (size_t)n));
+  w.d64 = reinterpret_cast<double *>(take(sizeof(double) * 2 * (size_t)n));
+  w.r64 = reinterpret_cast<double *>(take(sizeof(double) * 2 * (size_t)m));
+  w.partial = take(acc_bytes * (size_t)nchunk * m);
+  w.ctl = reinterpret_cast<RefineCtl *>(take(sizeof(RefineCtl)));
+  w.bytes = off;
+  return w;
+}
+
+// FP64 blocked MGS of [A64 b64] held in Q64 (m x (n+1)); R64 (n x (n+1))
+// receives R and, in its last column, y.
+int factor64(int m, int n, const RefineWork &w, int *info, hipStream_t st) {
+  const size_t planeQ = (size_t)m * (n + 1), planeR = (size_t)n * (n + 1);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(256), dim3(256), 0, st, w.R64, 2 * planeR);
+  const Shape sh = choose_shape(m, 1);
+  for (int k0 = 0; k0 < n; k0 += NBP) {
+    const int nb = n - k0 < NBP ? n - k0 : NBP;
+    StepArgs a;
+    a.m = m;
+    a.n = nb;
+    a.ncols = nb;
+    a.A = w.Q64 + (size_t)k0 * m;
+    a.lda = m;
+    a.planeA = planeQ;
+    a.b = nullptr;
+    a.Q = w.Q64 + (size_t)k0 * m;
+    a.ldq = m;
+    a.planeQ = planeQ;
+    a.R = w.R64 + (size_t)k0 * n + k0;
+    a.ldr = n;
+    a.planeR = planeR;
+    a.W = nullptr;
+    a.y = nullptr;
+    a.rho = nullptr;
+    a.info = info;
+    a.t = 0;
+    a.kbase = k0;
+    a.init_info = 0;
+    int rc = dispatch_shape<PrecD>(a, sh, st);
+    if (rc != MGS_OK) return rc;
+    const int N = n + 1 - (k0 + nb);  // trailing columns, b included
+    if (N > 0) {
+      const double *Qp = w.Q64 + (size_t)k0 * m;
+      double *At = w.Q64 + (size_t)(k0 + nb) * m;
+      double *Wb = w.R64 + (size_t)(k0 + nb) * n + k0;
+      hipLaunchKernelGGL(zgemm_qha_kernel, dim3(ceil_div(N, 16)), dim3(256), 0, st, m, N, nb, Qp, m, At, m, planeQ,
+                         Wb, n, planeR);
+      const int tiles = ceil_div(m, 16) * ceil_div(N, 16);
+      hipLaunchKernelGGL(zgemm_update_kernel, dim3(ceil_div(tiles, 4)), dim3(256), 0, st, m, N, nb, Qp, m, At, m,
+                         planeQ, Wb, n, planeR);
+    }
+    if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
+  }
+  return MGS_OK;
+}
+
+template <class P>
+int refine_solve(int m, int n, const double *A, int lda, const double *b, double *x, double tol, int max_iter,
+                 int *iters, double *err_est, void *work, int *info, hipStream_t st) {
+  RefineWork w = refine_layout(m, n, P::L, work);
+  const size_t planeQ = (size_t)m * (n + 1), planeR = (size_t)n * (n + 1);
+  hipLaunchKernelGGL((copy_hi_kernel<P::L>), dim3(ceil_div(m, 256), n + 1), dim3(256), 0, st, m, n, A, lda, b, w.Q64,
+                     w.ctl, info);
+  int rc = factor64(m, n, w, info, st);
+  if (rc != MGS_OK) return rc;
+  hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(64), 0, st, info, w.ctl);
+  const int *skip = &w.ctl->status;
+  // x0: R x0 = y (the last column of R64)
+  rc = backsolve_launch<PrecD>(n, w.R64, n, w.R64 + (size_t)n * n, w.d64, nullptr, st, planeR, skip, planeR);
+  if (rc != MGS_OK) return rc;
+  hipLaunchKernelGGL((set_x_kernel<P>), dim3(ceil_div(n, 256)), dim3(256), 0, st, n, w.d64, x);
+  const int nchunk = ceil_div(n, NBP);
+  for (int it = 1; it <= max_iter; ++it) {
+    hipLaunchKernelGGL((residual_partial_kernel<P>), dim3(ceil_div(m, 256), nchunk), dim3(256), 0, st, m, n, NBP, A,
+                       lda, b, x, static_cast<typename P::Acc *>(w.partial), w.ctl);
+    hipLaunchKernelGGL((residual_finish_kernel<P>), dim3(ceil_div(m, 256)), dim3(256), 0, st, m, nchunk,
+                       static_cast<const typename P::Acc *>(w.partial), w.r64, w.ctl);
+    for (int k0 = 0; k0 < n; k0 += NBP) {
+      const int nb = n - k0 < NBP ? n - k0 : NBP;
+      const double *Qp = w.Q64 + (size_t)k0 * m;
+      hipLaunchKernelGGL(proj_w_kernel, dim3(nb), dim3(256), 0, st, m, Qp, m, planeQ, w.r64, w.y64 + k0, (size_t)n,
+                         w.ctl);
+      hipLaunchKernelGGL(proj_r_kernel, dim3(ceil_div(m, 256)), dim3(256), 0, st, m, nb, Qp, m, planeQ, w.y64 + k0,
+                         (size_t)n, w.r64, w.ctl);
+    }
+    rc = backsolve_launch<PrecD>(n, w.R64, n, w.y64, w.d64, nullptr, st, planeR, skip);
+    if (rc != MGS_OK) return rc;
+    hipLaunchKernelGGL((refine_update_kernel<P>), dim3(1), dim3(256), 0, st, n, w.d64, x, tol, it, w.ctl);
+    if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
+  }
+  hipLaunchKernelGGL(refine_finish_kernel, dim3(1), dim3(64), 0, st, w.ctl, iters, err_est, info);
+  return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
+}
+
 }  // namespace
 
 extern "C" {
@@ -231,6 +363,7 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes) {
     case MGS_OP_QR: *bytes = qr_work_bytes(m, prec); return MGS_OK;
     case MGS_OP_SOLVE: *bytes = solve_work_bytes(n, prec); return MGS_OK;
     case MGS_OP_ADJOINT: *bytes = adjoint_work_bytes(m, n, prec); return MGS_OK;
+    case MGS_OP_REFINE: *bytes = refine_layout(m, n, prec, nullptr).bytes; return MGS_OK;
   }
   return MGS_ERR_UNSUPPORTED;
 }
@@ -267,6 +400,8 @@ int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq,
   a.rho = b ? rho : nullptr;
   a.info = info;
   a.t = 0;
+  a.kbase = 0;
+  a.init_info = 1;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (prec == 2) return dispatch_shape<PrecDD>(a, sh, st);
   return dispatch_shape<PrecQD>(a, sh, st);
@@ -312,6 +447,21 @@ int ls_adjoint(int m, int n, int prec, const double *A, int lda, const double *b
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (prec == 2) return adjoint_launch<PrecDD>(m, n, A, lda, b, Q, ldq, R, ldr, x, gx, gA, ldga, gb, work, info, st);
   return adjoint_launch<PrecQD>(m, n, A, lda, b, Q, ldq, R, ldr, x, gx, gA, ldga, gb, work, info, st);
+}
+
+int mgs_refine_solve(int m, int n, int prec, const double *A, int lda, const double *b, double *x, int block,
+                     double tol, int max_iter, int *iters, double *err_est, void *work, size_t work_bytes, int *info,
+                     mgs_stream_t stream) {
+  if (prec != 2 && prec != 4) return MGS_ERR_PREC;
+  if (n < 1 || m < n || m > max_rows(prec) || lda < m || max_iter < 0) return MGS_ERR_DIMS;
+  if (block != NBP) return MGS_ERR_UNSUPPORTED;
+  if (!aligned8(A) || !aligned8(b) || !aligned8(x) || !aligned8(work) || !aligned8(info)) return MGS_ERR_POINTER;
+  if (x == b || x == A) return MGS_ERR_POINTER;
+  if (work_bytes < refine_layout(m, n, prec, nullptr).bytes) return MGS_ERR_WORKSPACE;
+  if (!(tol >= 0.0)) return MGS_ERR_DIMS;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (prec == 2) return refine_solve<PrecDD>(m, n, A, lda, b, x, tol, max_iter, iters, err_est, work, info, st);
+  return refine_solve<PrecQD>(m, n, A, lda, b, x, tol, max_iter, iters, err_est, work, info, st);
 }
 
 }  // extern "C"

@@ -1,0 +1,318 @@
+// Precision form: FP64 blocked MGS factorisation with the trailing Gram and
+// update products on FP64 MFMA, then iterative refinement with the residual
+// and the solution accumulated in dd / qd.
+//
+// Factorisation of [A b] in FP64, panels of NB = 64 columns:
+//   factor panel p by MGS (Figure 1 restricted to the panel, the step
+//   kernel with plain complex doubles), then for the columns right of it,
+//   W = Q_p^H A_t (written into R) and A_t -= Q_p W.  b rides along as the
+//   last column, so its panel projections y_p = W(:, n) are those of the
+//   factorisation (the augmented semantics of Equation (1)).
+// Correction solve of A d = r: the same panel projections replayed on r
+// (w_p = Q_p^H r, r -= Q_p w_p), then back substitution with R.
+// Refinement: r = b - A x in dd / qd, d = FP64 solve of fl64(r),
+// x += d in dd / qd, until ||d|| <= tol ||x||, stagnation, or max_iter.
+#pragma once
+#include "mgs_kernels.hpp"
+
+namespace mgsq {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64 operand layout on gfx950 (checked on the device):
+// A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane
+// j + 16 (i % 4), register i / 4.
+__device__ __forceinline__ v4d mfma16x16x4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int NBP = 64;  // panel width of the blocked factorisation
+
+// W (NBP x N) = Q_p^H (NBP x m) A_t (m x N), complex, planar FP64.
+// Q_p: the panel's first column (plane stride plane), A_t: the first
+// trailing column, W: output with leading dimension ldw (R's block row).
+// One block = 4 waves = the 4 row tiles (16 panel columns each) of one
+// 16-column tile of W; K = m in steps of 4.
+__global__ __launch_bounds__(256) void zgemm_qha_kernel(int m, int N, int nbp, const double *Qp, int ldq,
+                                                         const double *At, int lda, size_t plane, double *W,
+                                                         int ldw, size_t planeW) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i0 = wave * 16;          // panel column tile
+  const int j0 = blockIdx.x * 16;    // trailing column tile
+  const int li = lane & 15, lk = lane >> 4;
+  const int qc = i0 + li;            // panel column read by this lane (A operand)
+  const int tc = j0 + li;            // trailing column read by this lane (B operand)
+  const bool qok = qc < nbp, tok = tc < N;
+  v4d cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+  const double *qr = Qp + (size_t)qc * ldq, *qi = qr + plane;
+  const double *ar = At + (size_t)tc * lda, *ai = ar + plane;
+  for (int k = 0; k < m; k += 4) {
+    const int row = k + lk;
+    const bool rok = row < m;
+    const double a_r = (qok && rok) ? qr[row] : 0.0, a_i = (qok && rok) ? qi[row] : 0.0;
+    const double b_r = (tok && rok) ? ar[row] : 0.0, b_i = (tok && rok) ? ai[row] : 0.0;
+    // conj(q) a: re = qr ar + qi ai, im = qr ai - qi ar
+    cr = mfma16x16x4(a_r, b_r, cr);
+    cr = mfma16x16x4(a_i, b_i, cr);
+    ci = mfma16x16x4(a_r, b_i, ci);
+    ci = mfma16x16x4(-a_i, b_r, ci);
+  }
+  const int oc = j0 + li;
+  if (oc < N) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int orow = i0 + lk + 4 * r;
+      if (orow < nbp) {
+        W[(size_t)oc * ldw + orow] = cr[r];
+        W[(size_t)oc * ldw + orow + planeW] = ci[r];
+      }
+    }
+  }
+}
+
+// A_t (m x N) -= Q_p (m x nbp) W (nbp x N).  One wave per 16 x 16 tile of
+// A_t, K = nbp in steps of 4.
+__global__ __launch_bounds__(256) void zgemm_update_kernel(int m, int N, int nbp, const double *Qp, int ldq,
+                                                            double *At, int lda, size_t plane, const double *W,
+                                                            int ldw, size_t planeW) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tiles_m = (m + 15) / 16;
+  const int tile = blockIdx.x * 4 + wave;
+  const int ti = tile % tiles_m, tj = tile / tiles_m;
+  if (tj * 16 >= N) return;
+  const int i0 = ti * 16, j0 = tj * 16;
+  const int li = lane & 15, lk = lane >> 4;
+  // output tile values (D layout): row i0 + lk + 4r, column j0 + li
+  const int oc = j0 + li;
+  v4d cr, ci;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int orow = i0 + lk + 4 * r;
+    const bool ok = oc < N && orow < m;
+    cr[r] = ok ? At[(size_t)oc * lda + orow] : 0.0;
+    ci[r] = ok ? At[(size_t)oc * lda + orow + plane] : 0.0;
+  }
+  const int arow = i0 + li;  // A operand row (Q_p)
+  const bool aok = arow < m;
+  for (int k = 0; k < nbp; k += 4) {
+    const int kk = k + lk;
+    const bool kok = kk < nbp;
+    const double q_r = (aok && kok) ? Qp[(size_t)kk * ldq + arow] : 0.0;
+    const double q_i = (aok && kok) ? Qp[(size_t)kk * ldq + arow + plane] : 0.0;
+    const double w_r = (kok && oc < N) ? W[(size_t)oc * ldw + kk] : 0.0;
+    const double w_i = (kok && oc < N) ? W[(size_t)oc * ldw + kk + planeW] : 0.0;
+    // a -= q w: re -= qr wr - qi wi, im -= qr wi + qi wr
+    cr = mfma16x16x4(-q_r, w_r, cr);
+    cr = mfma16x16x4(q_i, w_i, cr);
+    ci = mfma16x16x4(-q_r, w_i, ci);
+    ci = mfma16x16x4(-q_i, w_r, ci);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int orow = i0 + lk + 4 * r;
+    if (oc < N && orow < m) {
+      At[(size_t)oc * lda + orow] = cr[r];
+      At[(size_t)oc * lda + orow + plane] = ci[r];
+    }
+  }
+}
+
+// ------------------------------------------------------- refinement ------
+struct RefineCtl {
+  int status;  // 0 running, 1 converged, 2 stagnated, 3 factorisation failed
+  int iters;
+  double dprev;
+  double err_est;
+};
+
+// Columns of Q64 (m x (n+1), ld m) from the leading limbs of A and b.
+template <int L>
+__global__ __launch_bounds__(256) void copy_hi_kernel(int m, int n, const double *A, int lda, const double *b,
+                                                       double *Q64, RefineCtl *ctl, int *info) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (blockIdx.x == 0 && j == 0 && threadIdx.x == 0) {
+    ctl->status = 0;
+    ctl->iters = 0;
+    ctl->dprev = INFINITY;
+    ctl->err_est = INFINITY;
+    *info = 0;
+  }
+  if (i >= m) return;
+  const size_t plane64 = (size_t)m * (n + 1);
+  if (j < n) {
+    const size_t planeA = (size_t)lda * n;
+    Q64[(size_t)j * m + i] = A[(size_t)j * lda + i];
+    Q64[(size_t)j * m + i + plane64] = A[(size_t)j * lda + i + planeA];
+  } else {
+    Q64[(size_t)n * m + i] = b[i];
+    Q64[(size_t)n * m + i + plane64] = b[i + m];
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(double *p, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) p[i] = 0.0;
+}
+
+// r = b - A x in precision P, split over column chunks: block (rb, cb) sums
+// the columns [cb*CH, cb*CH + CH) of rows rb*256 .. into partial[cb][row].
+template <class P>
+__global__ __launch_bounds__(256) void residual_partial_kernel(int m, int n, int chunk, const double *A, int lda,
+                                                                const double *b, const double *x,
+                                                                typename P::Acc *partial, const RefineCtl *ctl) {
+  if (ctl->status != 0) return;
+  using Acc = typename P::Acc;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int cb = blockIdx.y;
+  if (i >= m) return;
+  const size_t planeA = (size_t)lda * n;
+  Acc acc;
+  if (cb == 0)
+    P::acc_set(acc, P::load(b + i, (size_t)m));
+  else
+    P::acc_zero(acc);
+  const int j1 = min(n, (cb + 1) * chunk);
+  for (int j = cb * chunk; j < j1; ++j)
+    P::acc_cmul(acc, P::load(A + (size_t)j * lda + i, planeA), P::cneg(P::load(x + j, (size_t)n)));
+  partial[(size_t)cb * m + i] = acc;
+}
+
+// Sum the chunk partials in chunk order; r64 = FP64 rounding of r.
+template <class P>
+__global__ __launch_bounds__(256) void residual_finish_kernel(int m, int nchunk, const typename P::Acc *partial,
+                                                               double *r64, const RefineCtl *ctl) {
+  if (ctl->status != 0) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  typename P::Acc acc = partial[i];
+  for (int c = 1; c < nchunk; ++c) P::acc_merge(acc, partial[(size_t)c * m + i]);
+  typename P::C v = P::acc_value(acc);
+  double tmp[2 * P::L];
+  P::store(tmp, 1, v);  // tmp[0] = re hi, tmp[1] = im hi (planes 0 and 1)
+  r64[i] = tmp[0];
+  r64[i + m] = tmp[1];
+}
+
+// w = Q_p^H r: one block per panel column, rows summed in a fixed order.
+__global__ __launch_bounds__(256) void proj_w_kernel(int m, const double *Qp, int ldq, size_t plane,
+                                                      const double *r, double *w, size_t planew,
+                                                      const RefineCtl *ctl) {
+  if (ctl->status != 0) return;
+  __shared__ double sr[4], si[4];
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double *qr = Qp + (size_t)c * ldq, *qi = qr + plane;
+  double ar = 0.0, ai = 0.0;
+  for (int i = tid; i < m; i += 256) {
+    const double xr = r[i], xi = r[i + m];
+    ar = __fma_rn(qr[i], xr, ar);
+    ar = __fma_rn(qi[i], xi, ar);
+    ai = __fma_rn(qr[i], xi, ai);
+    ai = __fma_rn(-qi[i], xr, ai);
+  }
+#pragma unroll
+  for (int mask = 32; mask >= 1; mask >>= 1) {
+    ar += __shfl_xor(ar, mask);
+    ai += __shfl_xor(ai, mask);
+  }
+  if (lane == 0) {
+    sr[wave] = ar;
+    si[wave] = ai;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    w[c] = ((sr[0] + sr[1]) + sr[2]) + sr[3];
+    w[c + planew] = ((si[0] + si[1]) + si[2]) + si[3];
+  }
+}
+
+// r -= Q_p w, one row per thread.
+__global__ __launch_bounds__(256) void proj_r_kernel(int m, int nbp, const double *Qp, int ldq, size_t plane,
+                                                      const double *w, size_t planew, double *r,
+                                                      const RefineCtl *ctl) {
+  if (ctl->status != 0) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  double xr = r[i], xi = r[i + m];
+  for (int c = 0; c < nbp; ++c) {
+    const double qr = Qp[(size_t)c * ldq + i], qi = Qp[(size_t)c * ldq + i + plane];
+    const double wr = w[c], wi = w[c + planew];
+    xr = __fma_rn(-qr, wr, xr);
+    xr = __fma_rn(qi, wi, xr);
+    xi = __fma_rn(-qr, wi, xi);
+    xi = __fma_rn(-qi, wr, xi);
+  }
+  r[i] = xr;
+  r[i + m] = xi;
+}
+
+// The FP64 solution as the dd / qd starting x (first solve).
+template <class P>
+__global__ __launch_bounds__(256) void set_x_kernel(int n, const double *x64, double *x) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  for (int p = 0; p < 2 * P::L; ++p) x[i + (size_t)p * n] = (p < 2) ? x64[i + (size_t)p * n] : 0.0;
+}
+
+// x += d (d in FP64), with the stopping test on ||d|| and ||x||: stop when
+// ||d|| <= tol ||x|| (converged) or ||d|| > ||d_prev|| / 2 (stalled).  One block.
+template <class P>
+__global__ __launch_bounds__(256) void refine_update_kernel(int n, const double *d64, double *x, double tol,
+                                                             int iter, RefineCtl *ctl) {
+  if (ctl->status != 0) return;
+  __shared__ double red[2][4];
+  __shared__ int stag;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double dn = 0.0, xn = 0.0;
+  for (int i = tid; i < n; i += 256) {
+    const double dr = d64[i], di = d64[i + n];
+    dn = __fma_rn(dr, dr, __fma_rn(di, di, dn));
+    const double xr = x[i], xi = x[i + n];
+    xn = __fma_rn(xr, xr, __fma_rn(xi, xi, xn));
+  }
+#pragma unroll
+  for (int mask = 32; mask >= 1; mask >>= 1) {
+    dn += __shfl_xor(dn, mask);
+    xn += __shfl_xor(xn, mask);
+  }
+  if (lane == 0) {
+    red[0][wave] = dn;
+    red[1][wave] = xn;
+  }
+  __syncthreads();
+  dn = sqrt(((red[0][0] + red[0][1]) + red[0][2]) + red[0][3]);
+  xn = sqrt(((red[1][0] + red[1][1]) + red[1][2]) + red[1][3]);
+  if (tid == 0) stag = (iter > 1 && dn > 0.5 * ctl->dprev) ? 1 : 0;
+  __syncthreads();
+  if (stag) {
+    // The corrections stopped shrinking: converged to the attainable
+    // accuracy when the last applied one was already below sqrt(tol) of x,
+    // a failure otherwise.  The stalled correction is not applied.
+    if (tid == 0) ctl->status = (ctl->err_est <= sqrt(tol)) ? 1 : 2;
+    return;
+  }
+  for (int i = tid; i < n; i += 256) {
+    typename P::C v = P::load(x + i, (size_t)n);
+    P::add_cd(v, d64[i], d64[i + n]);
+    P::store(x + i, (size_t)n, v);
+  }
+  if (tid == 0) {
+    ctl->iters = iter;
+    ctl->err_est = xn > 0.0 ? dn / xn : dn;
+    ctl->dprev = dn;
+    if (dn <= tol * xn) ctl->status = 1;
+  }
+}
+
+// Skip the refinement when the factorisation reported a bad column.
+__global__ void refine_check_kernel(const int *info, RefineCtl *ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && *info != 0) ctl->status = 3;
+}
+
+__global__ void refine_finish_kernel(const RefineCtl *ctl, int *iters, double *err_est, int *info) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (iters) *iters = ctl->iters;
+  if (err_est) *err_est = ctl->err_est;
+  if (*info == 0) *info = ctl->status == 1 ? 0 : (ctl->status == 2 ? -1 : -2);
+}
+
+}  // namespace mgsq

@@ -24,6 +24,11 @@ Section 4):
   column j scaled by fl(10^s_j), s_j ~ U[-12,12]; each entry is the exact
   dd product of the scale and the Gaussian; x_true complex N(0,1);
   b = A x_true to dd accuracy.
+* ``config4`` -- n x n (2048) A = U diag(sigma) V^H in FP64, U and V products
+  of 4 Householder reflectors with complex N(0,1) vectors, sigma geometric
+  from 1 to 1e-10; x_true complex N(0,1); b = A x_true rounded to qd from the
+  exact sum, so that x_true solves the stored system to about
+  kappa 2^-212 (the reference for the precision form).
 * ``config5`` -- dd, 512 x 384, A, b, g with N(0,1) hi limbs.
 * ``table2_matrix`` -- 32 x 32 entries r e^{i theta}, theta ~ U[0, 2 pi),
   log10 r ~ U[-g, g] (Section 4, Table 2).
@@ -116,10 +121,25 @@ def _round_int(t, S, L):
     return limbs
 
 
-def exact_matvec(A, x, L_out, extra=None):
+def _exact_rows(args):
+    """Rows [i0, i1) of the exact product, rounded to L_out limbs."""
+    Ar, Ai, xr, xi, er, ei, m, n, i0, i1, S, L_out = args
+    out = np.zeros((L_out, 2, i1 - i0))
+    for i in range(i0, i1):
+        sr, si = er[i], ei[i]
+        for j in range(n):
+            a_r, a_i = Ar[j * m + i], Ai[j * m + i]
+            sr += a_r * xr[j] - a_i * xi[j]
+            si += a_r * xi[j] + a_i * xr[j]
+        out[:, 0, i - i0] = _round_int(sr, 2 * S, L_out)
+        out[:, 1, i - i0] = _round_int(si, 2 * S, L_out)
+    return out
+
+
+def exact_matvec(A, x, L_out, extra=None, workers=1):
     """Round-to-L_out-limbs of the exact product A x (+ extra), Python integers.
 
-    For small problems only (m n of a few 10^5).
+    Rows are independent; `workers` > 1 splits them over forked processes.
     """
     La, _, n, m = A.shape
     S = 1200
@@ -135,16 +155,23 @@ def exact_matvec(A, x, L_out, extra=None):
     else:
         er = [0] * m
         ei = [0] * m
-    b = np.zeros((L_out, 2, m))
-    for i in range(m):
-        sr, si = er[i], ei[i]
-        for j in range(n):
-            a_r, a_i = Ar[j * m + i], Ai[j * m + i]
-            sr += a_r * xr[j] - a_i * xi[j]
-            si += a_r * xi[j] + a_i * xr[j]
-        b[:, 0, i] = _round_int(sr, 2 * S, L_out)
-        b[:, 1, i] = _round_int(si, 2 * S, L_out)
-    return b
+    if workers <= 1 or m < 64:
+        return _exact_rows((Ar, Ai, xr, xi, er, ei, m, n, 0, m, S, L_out))
+    import multiprocessing as mp
+    bounds = np.linspace(0, m, workers + 1).astype(int)
+    global _EXACT_SHARED
+    _EXACT_SHARED = (Ar, Ai, xr, xi, er, ei)
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_exact_rows_shared, [(m, n, int(a), int(b), S, L_out) for a, b in zip(bounds[:-1], bounds[1:])])
+    return np.concatenate(parts, axis=2)
+
+
+_EXACT_SHARED = None
+
+
+def _exact_rows_shared(args):
+    m, n, i0, i1, S, L_out = args
+    return _exact_rows(_EXACT_SHARED + (m, n, i0, i1, S, L_out))
 
 
 def _split(a):
@@ -230,6 +257,27 @@ def config3(system=0, m=1024, n=1024):
     x2[0] = x[0]
     return dict(A=np.ascontiguousarray(A), b=np.ascontiguousarray(b), x_true=x2, prec=2, m=m, n=n,
                 scales=c)
+
+
+def config4(n=2048, reflectors=4, cond=1e10, workers=1):
+    """Precision-form workload: FP64 A = U diag(sigma) V^H, b exact to qd."""
+    g = rng(4, 0, 5)
+    sigma = cond ** (-np.arange(n) / (n - 1.0))
+    M = np.diag(sigma).astype(np.complex128)
+    for _ in range(reflectors):  # M <- M H, H = I - 2 v v^H / (v^H v)
+        v = g.standard_normal(n) + 1j * g.standard_normal(n)
+        M = M - (2.0 / np.vdot(v, v).real) * np.outer(M @ v, v.conj())
+    for _ in range(reflectors):  # M <- H M
+        u = g.standard_normal(n) + 1j * g.standard_normal(n)
+        M = M - (2.0 / np.vdot(u, u).real) * np.outer(u, u.conj() @ M)
+    A1 = np.zeros((1, 2, n, n))
+    A1[0, 0] = M.real.T
+    A1[0, 1] = M.imag.T
+    xg = rng(4, 0, 1)
+    x = np.zeros((1, 2, n))
+    x[0] = xg.standard_normal((2, n))
+    b4 = exact_matvec(A1, x, 4, workers=workers)
+    return dict(A64=np.ascontiguousarray(A1), b4=b4, x_true=x, sigma=sigma, n=n, m=n)
 
 
 def config5():

@@ -1,0 +1,77 @@
+"""GPU checks of the precision form (mgs_refine_solve).
+
+Reference: config4 builds b as the exact product A x_true rounded to qd, so
+x_true solves the stored system to about kappa 2^-212 (1e-53 at kappa 1e10).
+Bar: the refined dd / qd solution is at least as accurate as the plain dd /
+qd MGS solution on the same GPU (within a factor 10), and converges.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1210_0800_amd import api, inputs  # noqa: E402
+from tests._parity import diff, value  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def planar(X, L):
+    """First L limbs of a normalized expansion (zero-padded): for a qd vector
+    truncated to dd this is within one dd ulp of its rounding."""
+    Y = np.zeros((L,) + X.shape[1:])
+    k = min(L, X.shape[0])
+    Y[:k] = X[:k]
+    return Y
+
+
+def rel_err(x, x_true):
+    X = np.zeros((4,) + x.shape[1:])
+    X[: x.shape[0]] = x
+    Xt = np.zeros((4,) + x_true.shape[1:])
+    Xt[: x_true.shape[0]] = x_true
+    d = diff(X, Xt)
+    return float(np.sqrt(np.sum(d ** 2)) / np.sqrt(np.sum(value(Xt) ** 2)))
+
+
+def solve_both(d, L, max_iter=30):
+    A = planar(d["A64"], L)
+    b = d["b4"][:L].copy()
+    Ag, bg = T(A), T(b)
+    f = api.lstsq(Ag, bg)
+    r = api.refine_lstsq(Ag, bg, max_iter=max_iter)
+    torch.cuda.synchronize()
+    assert int(f["info"].item()) == 0
+    plain = rel_err(f["x"].cpu().numpy(), d["x_true"])
+    refined = rel_err(r["x"].cpu().numpy(), d["x_true"])
+    return plain, refined, int(r["iters"].item()), int(r["info"].item()), float(r["err_est"].item())
+
+
+@pytest.mark.parametrize("L", [2, 4])
+def test_refined_matches_plain_accuracy_n256(L):
+    d = inputs.config4(256)
+    plain, refined, iters, info, est = solve_both(d, L)
+    print("n=256 L=%d plain %.3e refined %.3e iters %d info %d est %.2e" % (L, plain, refined, iters, info, est))
+    assert info == 0 and 1 <= iters <= 25
+    assert refined <= 10 * max(plain, (1e-30 if L == 2 else 1e-60))
+    assert plain <= (1e-19 if L == 2 else 1e-49)
+
+
+def test_refined_dd_config4_2048():
+    d = inputs.config4(2048, workers=8)
+    plain, refined, iters, info, est = solve_both(d, 2)
+    print("n=2048 dd plain %.3e refined %.3e iters %d info %d" % (plain, refined, iters, info))
+    assert info == 0 and iters <= 12
+    assert refined <= 10 * plain
+
+
+def test_refinement_reports_failure_to_converge():
+    d = inputs.config4(128, cond=1e19)
+    A = planar(d["A64"], 2)
+    r = api.refine_lstsq(T(A), T(d["b4"][:2].copy()), max_iter=8)
+    torch.cuda.synchronize()
+    assert int(r["info"].item()) in (-1, -2)
