@@ -168,7 +168,7 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "mgs_step_kernel (all launches of one factorisation)",
+            "kernel": "mgs_resident_kernel (one cooperative launch per factorisation)",
             "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",

@@ -32,7 +32,9 @@
  * Numerical status goes to the device int *info (written by the kernels):
  *   0 = success; k > 0 = column k (1-based) had a zero or non-finite norm
  *   (MGS does not pivot, Section 4), outputs from column k on are then
- *   unspecified.
+ *   unspecified; MGS_INFO_SYNC_TIMEOUT = a wait between workgroups of the
+ *   single-launch factorisation exceeded its time limit (outputs
+ *   unspecified; not expected in normal operation).
  * ------------------------------------------------------------------------
  */
 #ifndef MGSQR_H
@@ -59,6 +61,9 @@ enum {
   MGS_ERR_UNSUPPORTED = -6  /* unknown operation code */
 };
 
+/* *info value of a factorisation whose inter-workgroup wait timed out. */
+#define MGS_INFO_SYNC_TIMEOUT (-9)
+
 enum { MGS_OP_QR = 0, MGS_OP_SOLVE = 1, MGS_OP_ADJOINT = 2, MGS_OP_REFINE = 3 };
 
 /* Largest supported row count m: dd 4096, qd 2048. */
@@ -68,10 +73,10 @@ enum { MGS_OP_QR = 0, MGS_OP_SOLVE = 1, MGS_OP_ADJOINT = 2, MGS_OP_REFINE = 3 };
 int mgs_abi_version(void);
 const char *mgs_status_string(int status);
 
-/* Bytes of device workspace needed by operation `op` (MGS_OP_QR with a
- * right-hand side, MGS_OP_SOLVE, MGS_OP_ADJOINT, MGS_OP_REFINE) for an
- * m x n problem;
- * written to *bytes. */
+/* Bytes of device workspace needed by operation `op` (MGS_OP_QR,
+ * MGS_OP_SOLVE, MGS_OP_ADJOINT, MGS_OP_REFINE) for an m x n problem;
+ * written to *bytes.  A workspace may be reused by later calls on the same
+ * stream; calls that may overlap need distinct workspaces. */
 int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
 
 /*
@@ -89,9 +94,17 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
  *             of the projected right-hand side, ||b - A x|| of the
  *             least-squares solution x (Equation (1)).
  *   work      workspace of mgs_workspace_size(m, n, prec, MGS_OP_QR) bytes
- *             when b != NULL (may be NULL otherwise).
+ *             (always required: it holds the publication counter of the
+ *             single-launch factorisation and the working copy of b).
  *   info      device int, see above.
  * Requires 1 <= n <= m <= MGS_MAX_ROWS_{DD,QD}.
+ * Schedule: in dd, when every column fits in the register file of the
+ * device (m <= 1024 and at most 5 columns per compute unit, 8 when m <= 512,
+ * e.g. 1024 x 1024 with b on 256 compute units) the factorisation is one
+ * cooperative launch with the columns held in registers; otherwise (and in
+ * qd) one launch per panel of columns.
+ * Both schedules perform the operations of Figure 1 in the same order per
+ * column; reduction trees differ, so results agree to rounding.
  */
 int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq, double *R, int ldr,
            const double *b, double *y, double *rho, void *work, size_t work_bytes, int *info,

@@ -57,10 +57,10 @@ def mgs_qr(A, b=None, *, Q=None, R=None, y=None, rho=None, info=None, work=None,
         y = torch.empty((prec, 2, n), dtype=torch.float64, device=dev) if y is None else y
         if with_rho and rho is None:
             rho = torch.empty(prec, dtype=torch.float64, device=dev)
-        work = workspace(m, n, prec, _lib.MGS_OP_QR, dev) if work is None else work
     else:
         y = rho = None
-    nwork = 0 if work is None else work.numel() * work.element_size()
+    work = workspace(m, n, prec, _lib.MGS_OP_QR, dev) if work is None else work
+    nwork = work.numel() * work.element_size()
     st = _lib.lib().mgs_qr(m, n, prec, _ptr(A), m, _ptr(Q), m, _ptr(R), R.shape[3], _ptr(b), _ptr(y),
                            _ptr(rho), _ptr(work), nwork, _ptr(info), _stream(A))
     _lib.check("mgs_qr", st)

@@ -84,7 +84,6 @@ template <class P>
 __global__ __launch_bounds__(WG) void adj_gemv_kernel(int m, int n, const double *Q, int ldq, size_t planeQ,
                                                        const double *A, int lda, size_t planeA, const double *b,
                                                        const double *x, const double *w, double *gb, double *r) {
-  using C = typename P::C;
   using Acc = typename P::Acc;
   const int i = blockIdx.x * WG + threadIdx.x;
   if (i >= m) return;

@@ -6,10 +6,13 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
+#include <cstring>
 
 #include "adjoint_kernels.hpp"
 #include "mgs_kernels.hpp"
 #include "precision_kernels.hpp"
+#include "resident_kernels.hpp"
 
 using namespace mgsq;
 
@@ -176,7 +179,10 @@ int project_launch(int m, int n, const double *Q, int ldq, const double *b, doub
   return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
 }
 
-size_t qr_work_bytes(int m, int prec) { return round256(sizeof(double) * 2 * (size_t)prec * m); }
+// QR: working copy of b (2Lm doubles), then the synchronisation words of
+// the single-launch schedule.
+size_t qr_w_bytes(int m, int prec) { return round256(sizeof(double) * 2 * (size_t)prec * m); }
+size_t qr_work_bytes(int m, int prec) { return qr_w_bytes(m, prec) + sizeof(unsigned int) * RES_SYNC_WORDS; }
 size_t solve_work_bytes(int n, int prec) { return round256(sizeof(double) * 2 * (size_t)prec * n); }
 // adjoint: w (n), z (n), r (m)
 size_t adjoint_work_bytes(int m, int n, int prec) {
@@ -336,6 +342,149 @@ int refine_solve(int m, int n, const double *A, int lda, const double *b, double
   return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
 }
 
+// ------------------------------------------- single-launch schedule --------
+struct DevInfo {
+  int cus;
+  long long wclk_khz;
+};
+bool dev_info(DevInfo &d) {
+  static DevInfo cache[64];
+  static bool have[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+  if (!have[dev]) {
+    int cus = 0, wclk = 0, coop = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return false;
+    cache[dev].cus = coop ? cus : 0;
+    cache[dev].wclk_khz = wclk > 0 ? wclk : 100000;
+    have[dev] = true;
+  }
+  d = cache[dev];
+  return d.cus > 0;
+}
+
+// Columns held by the workgroup holding the most, for panels of bw columns
+// dealt in the reflected cyclic order of the resident kernel.
+int res_max_cols(int ncols, int bw, int G) {
+  const int np = ceil_div(ncols, bw);
+  int best = 0;
+  for (int g = 0; g < G; ++g) {
+    int cnt = 0;
+    for (int i = 0;; ++i) {
+      const int qi = 2 * G * (i / 2) + ((i & 1) ? 2 * G - 1 - g : g);
+      if (qi >= np) break;
+      const int p = np - 1 - qi;
+      cnt += (ncols - p * bw < bw) ? ncols - p * bw : bw;
+    }
+    if (cnt > best) best = cnt;
+  }
+  return best;
+}
+
+// Resident shapes (dd): workgroups of RES_NW waves (2 per SIMD), RR rows
+// per thread, CB column slots per workgroup (register budget 256 per lane).
+constexpr int RES_NW = 8;
+constexpr int res_cb(int rr) { return rr == 1 ? 8 : 5; }
+
+struct ResPlan {
+  int rr, bw, np, G;
+};
+bool res_choose(int m, int ncols, int cus, ResPlan &pl) {
+  const int rr = pow2_at_least(ceil_div(m, 64 * RES_NW));
+  if (rr > 2) return false;
+  const int cb = res_cb(rr);
+  const int bws[3] = {2, 1, 4};
+  for (int bw : bws) {
+    const int np = ceil_div(ncols, bw);
+    const int G = np < cus ? np : cus;
+    if (res_max_cols(ncols, bw, G) <= cb) {
+      pl.rr = rr;
+      pl.bw = bw;
+      pl.np = np;
+      pl.G = G;
+      return true;
+    }
+  }
+  return false;
+}
+
+// Returns 1 when the single launch does not apply here (the caller then
+// takes the per-panel schedule).
+template <class P, int RR>
+int res_launch_rr(ResArgs a, int cus, hipStream_t st) {
+  constexpr int CB = res_cb(RR);
+  auto kern = mgs_resident_kernel<P, RR, CB, RES_NW>;
+  // Only kernels that keep everything in registers and LDS take this
+  // schedule: no private (scratch) memory in a cooperative launch.
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kern)) != hipSuccess || fa.localSizeBytes != 0)
+    return 1;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), 64 * RES_NW, 0) !=
+      hipSuccess)
+    return 1;
+  if ((long long)per_cu * cus < a.G) return 1;
+  hipLaunchKernelGGL(resident_init_kernel, dim3(1), dim3(RES_SYNC_WORDS), 0, st, a.sync, a.info, 1);
+  if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
+  void *args[] = {&a};
+  if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(a.G), dim3(64 * RES_NW), args, 0, st) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return MGS_OK;
+}
+
+// dd only: the qd instantiations do not fit in registers.
+int res_launch_dd(const StepArgs &s, void *sync, hipStream_t st) {
+  using P = PrecDD;
+  DevInfo d;
+  if (!dev_info(d)) return 1;
+  ResPlan pl;
+  if (!res_choose(s.m, s.ncols, d.cus, pl)) return 1;
+  ResArgs a;
+  a.m = s.m;
+  a.n = s.n;
+  a.ncols = s.ncols;
+  a.A = s.A;
+  a.lda = s.lda;
+  a.planeA = s.planeA;
+  a.b = s.b;
+  a.Q = s.Q;
+  a.ldq = s.ldq;
+  a.planeQ = s.planeQ;
+  a.R = s.R;
+  a.ldr = s.ldr;
+  a.planeR = s.planeR;
+  a.y = s.y;
+  a.rho = s.rho;
+  a.info = s.info;
+  a.sync = static_cast<unsigned int *>(sync);
+  a.bw = pl.bw;
+  a.np = pl.np;
+  a.G = pl.G;
+  a.xcd_group = pl.G % 8 == 0 ? pl.G / 8 : 0;
+  a.spin_ticks = d.wclk_khz * 2000;  // 2 s
+  switch (pl.rr) {
+    case 1: return res_launch_rr<P, 1>(a, d.cus, st);
+    case 2: return res_launch_rr<P, 2>(a, d.cus, st);
+  }
+  return 1;
+}
+
+// Schedule override: MGSQR_SCHEDULE=panel forces one launch per panel,
+// =resident requires the single launch (MGS_ERR_DIMS when it does not
+// apply); unset or any other value chooses automatically.
+int schedule_mode() {
+  const char *e = std::getenv("MGSQR_SCHEDULE");
+  if (e == nullptr) return 0;
+  if (std::strcmp(e, "panel") == 0) return 1;
+  if (std::strcmp(e, "resident") == 0) return 2;
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -376,10 +525,9 @@ int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq,
   if (!aligned8(A) || !aligned8(Q) || !aligned8(R) || !aligned8(info)) return MGS_ERR_POINTER;
   if (Q == A && ldq != lda) return MGS_ERR_POINTER;
   if (rho && !aligned8(rho)) return MGS_ERR_POINTER;
-  if (b) {
-    if (!aligned8(b) || !aligned8(y) || !aligned8(work)) return MGS_ERR_POINTER;
-    if (work_bytes < qr_work_bytes(m, prec)) return MGS_ERR_WORKSPACE;
-  }
+  if (!aligned8(work)) return MGS_ERR_POINTER;
+  if (b && (!aligned8(b) || !aligned8(y))) return MGS_ERR_POINTER;
+  if (work_bytes < qr_work_bytes(m, prec)) return MGS_ERR_WORKSPACE;
   Shape sh = choose_shape(m, prec);
   StepArgs a;
   a.m = m;
@@ -403,6 +551,13 @@ int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq,
   a.kbase = 0;
   a.init_info = 1;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int mode = schedule_mode();
+  if (mode != 1) {
+    void *sync = static_cast<char *>(work) + qr_w_bytes(m, prec);
+    const int rc = prec == 2 ? res_launch_dd(a, sync, st) : 1;
+    if (rc != 1) return rc;
+    if (mode == 2) return MGS_ERR_DIMS;
+  }
   if (prec == 2) return dispatch_shape<PrecDD>(a, sh, st);
   return dispatch_shape<PrecQD>(a, sh, st);
 }

@@ -1,0 +1,516 @@
+// Register-resident MGS: the whole factorisation of [A b] in one persistent
+// launch, every column held in registers from its first load to the
+// moment its q vector is written.
+//
+// Operations are those of Figure 1 (Section 3) on the augmented matrix of
+// Equation (1): column j receives the projections k = 1, 2, ..., j-1 in
+// order, then (j <= n) its norm r_jj and q_j = a_j / r_jj.  Only the
+// schedule is new:
+//
+//  * The columns are cut into panels of `bw` consecutive columns.  Panel
+//    p belongs to one workgroup; the NW waves of a workgroup split the
+//    rows (thread t holds rows r*64*NW + t, r < RR, of every column it
+//    owns), so inner products and norms are wave scans plus an NW-way
+//    exchange through LDS, and each projection costs one block barrier.
+//    Several waves per SIMD (NW = 8 or 16) hide the latency of the
+//    dependent double-double operations.
+//  * Panels are dealt to the G workgroups in a reflected cyclic order
+//    counted from the last panel (workgroup g gets panels np-1-g,
+//    np-1-(2G-1-g), np-1-(2G+g), ...), so that every workgroup owns about
+//    the same triangular amount of work (a late and an early panel).
+//  * q_k is published by its owner through the output Q and one counter
+//    of published columns per wave: wave w of every workgroup holds the
+//    same rows (r*64*NW + 64w + lane), so wave w of a consumer only needs the
+//    rows written by wave w of the producer.  The producer wave writes its
+//    rows with device-scope (write-through) stores, waits for them to
+//    complete, then stores the counter; the consumer wave polls its
+//    counter and reads the rows with device-scope loads.  Neither side
+//    needs a workgroup barrier, an L2 write-back or an L2 invalidation.
+//    Publication is in the order k = 0, 1, ..., so one counter per wave
+//    covers every column.
+//  * Critical path first: when the q that completes a workgroup's next
+//    panel arrives, it is applied to that panel only, the panel is factored
+//    and published, and only then are the deferred projections applied to
+//    the workgroup's later columns (still in the order k, k+1, ...).
+//  * Consecutive panels sit on the same XCD (workgroup numbering is
+//    rotated so that logical workgroups 0..G/8-1 land on one XCD), so most
+//    hand-offs stay inside one L2.
+//
+// The launch is cooperative (every workgroup resident), and every wait is
+// bounded by a wall-clock limit after which the kernel aborts through a
+// flag that all waits observe, so no wave can spin forever.
+#pragma once
+#include "../../include/mgsqr.h"
+#include "mgs_kernels.hpp"
+
+namespace mgsq {
+
+struct ResArgs {
+  int m, n, ncols;  // ncols = n + 1 when b is augmented
+  const double *A;
+  int lda;
+  size_t planeA;
+  const double *b;
+  double *Q;
+  int ldq;
+  size_t planeQ;
+  double *R;
+  int ldr;
+  size_t planeR;
+  double *y;
+  double *rho;
+  int *info;
+  unsigned int *sync;  // RES_SYNC_WORDS words, zero at launch: per-wave counters and the abort flag
+  int bw, np, G;
+  int xcd_group;        // logical workgroups per XCD (G / 8), 0 for identity numbering
+  long long spin_ticks;  // wall-clock limit of one wait
+};
+
+// Sentinel column index of an empty slot.
+constexpr int RES_NONE = 1 << 30;
+
+// Synchronisation words: wave w's counter at 16 w (w < 16, one 64-byte
+// line each), the abort flag in the last word.
+constexpr int RES_SYNC_WORDS = 256;
+constexpr int RES_ABORT = RES_SYNC_WORDS - 1;
+
+// Device-scope (coherent across XCDs) relaxed loads and stores of one
+// double: the q vectors exchanged between workgroups.
+__device__ __forceinline__ void coh_store(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double coh_load(const double *p) {
+  return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until wave `wave` of the owners has published at least k+1
+// columns.  `seen` caches the last observed count (wave-uniform).
+// Returns false on abort or time-out.
+__device__ __forceinline__ bool res_wait(const ResArgs &a, int k, int wave, int &seen) {
+  if (seen > k) return true;
+  const long long t0 = wall_clock64();
+  unsigned int *cnt = a.sync + 16 * wave;
+  while (true) {
+    const int v = __builtin_amdgcn_readfirstlane(
+        (int)__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (v > k) {
+      seen = v;
+      asm volatile("" ::: "memory");
+      return true;
+    }
+    if (__builtin_amdgcn_readfirstlane(
+            (int)__hip_atomic_load(a.sync + RES_ABORT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)
+      return false;
+    if (wall_clock64() - t0 > a.spin_ticks) {
+      __hip_atomic_store(a.sync + RES_ABORT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(a.info, MGS_INFO_SYNC_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// Wave reduction by DPP: an inclusive scan inside each row of 16 lanes
+// (shifts 1, 2, 4, 8), then the row totals carried across rows; lane 63
+// ends with the sum of all 64 lanes (a fixed merge tree, so results are
+// reproducible).  Lanes shifted in from outside a row read zero, which
+// the accumulator merge adds exactly.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_shift(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void dpp_step(PrecDD::Acc &a, bool re_only) {
+  PrecDD::Acc o;
+  o.sr = dpp_shift<CTRL, ROWS>(a.sr);
+  o.cr = dpp_shift<CTRL, ROWS>(a.cr);
+  if (re_only) {
+    PrecDD::acc_merge_re(a, o);
+  } else {
+    o.si = dpp_shift<CTRL, ROWS>(a.si);
+    o.ci = dpp_shift<CTRL, ROWS>(a.ci);
+    PrecDD::acc_merge(a, o);
+  }
+}
+__device__ __forceinline__ void wave_sum_dpp(PrecDD::Acc &a, bool re_only) {
+  dpp_step<0x111, 0xf>(a, re_only);  // row_shr:1
+  dpp_step<0x112, 0xf>(a, re_only);  // row_shr:2
+  dpp_step<0x114, 0xf>(a, re_only);  // row_shr:4
+  dpp_step<0x118, 0xf>(a, re_only);  // row_shr:8
+  dpp_step<0x142, 0xa>(a, re_only);  // row_bcast:15 into rows 1, 3
+  dpp_step<0x143, 0xc>(a, re_only);  // row_bcast:31 into rows 2, 3
+}
+
+template <class P, int RR, int CB, int NW>
+struct Resident {
+  using C = typename P::C;
+  using Acc = typename P::Acc;
+  using Rl = typename P::R;
+  static constexpr int RWG = 64 * NW;  // threads per workgroup
+
+  const ResArgs &a;
+  int tid, wave, lane;
+  int cidx[CB];  // column of each slot, ascending; RES_NONE when empty
+  C col[CB][RR];
+  Acc (*part)[NW][CB];     // LDS: [2][NW][CB] partial sums
+  double *qdef;            // LDS: thread-private spill of a deferred q
+  int par;
+
+  __device__ __forceinline__ Resident(const ResArgs &args, Acc (*p)[NW][CB], double *qd)
+      : a(args), part(p), qdef(qd), par(0) {
+    tid = threadIdx.x;
+    wave = tid >> 6;
+    lane = tid & 63;
+  }
+
+  // Sum of the wave partials [W0, W0 + CNT) of slot s in a fixed pairwise
+  // tree (the same in every thread; few partials live at a time).
+  template <int W0, int CNT>
+  __device__ __forceinline__ Acc merge_tree(int s, bool re_only) const {
+    if constexpr (CNT == 1) {
+      return part[par][W0][s];
+    } else {
+      Acc x = merge_tree<W0, CNT / 2>(s, re_only);
+      const Acc y = merge_tree<W0 + CNT / 2, CNT / 2>(s, re_only);
+      if (re_only)
+        P::acc_merge_re(x, y);
+      else
+        P::acc_merge(x, y);
+      return x;
+    }
+  }
+  __device__ __forceinline__ Acc merge_parts(int s, bool re_only) const { return merge_tree<0, NW>(s, re_only); }
+
+  // r_kj for the slots s whose column lies in (k, hi) and >= lo: the inner
+  // products of q with those columns, one block reduction, the R / y
+  // stores and the updates a_j -= r_kj q.
+  __device__ __forceinline__ void apply(const C (&q)[RR], int k, int lo, int hi) {
+    Acc acc[CB];
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      P::acc_zero(acc[s]);
+      const int j = cidx[s];
+      if (j > k && j >= lo && j < hi) {
+#pragma unroll
+        for (int r = 0; r < RR; ++r) P::acc_cmulc(acc[s], q[r], col[s][r]);
+      }
+    });
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      const int j = cidx[s];
+      if (j > k && j >= lo && j < hi) {
+        wave_sum_dpp(acc[s], false);
+        if (lane == 63) part[par][wave][s] = acc[s];
+      }
+    });
+    lds_barrier();
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      const int j = cidx[s];
+      if (j > k && j >= lo && j < hi) {
+        const C rk = P::acc_value(merge_parts(s, false));
+        if (tid == 0) {
+          if (j < a.n)
+            P::store(a.R + (size_t)j * a.ldr + k, a.planeR, rk);
+          else
+            P::store(a.y + k, (size_t)a.n, rk);
+        }
+#pragma unroll
+        for (int r = 0; r < RR; ++r) P::upd(col[s][r], rk, q[r]);
+      }
+    });
+    par ^= 1;
+  }
+
+  // r_kk = ||a_k||, q_k = a_k / r_kk for the slot holding column k; q_k
+  // and R(k, k) are written, then published.  On return q holds q_k (this
+  // thread's rows).
+  __device__ __forceinline__ void normalize(int k, C (&q)[RR]) {
+    Acc nacc;
+    P::acc_zero(nacc);
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      if (cidx[s] == k) {
+#pragma unroll
+        for (int r = 0; r < RR; ++r) P::acc_abs2(nacc, col[s][r]);
+      }
+    });
+    wave_sum_dpp(nacc, true);
+    if (lane == 63) part[par][wave][0] = nacc;
+    lds_barrier();
+    const Rl s2 = P::acc_value_re(merge_parts(0, true));
+    par ^= 1;
+    if (!P::ok_norm(s2) && tid == 0) atomicCAS(a.info, 0, k + 1);
+    const Rl rkk = P::sqrt_(s2);
+    const Rl inv = P::recip(rkk);
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      if (cidx[s] == k) {
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+          col[s][r] = P::scale(col[s][r], inv);
+          q[r] = col[s][r];
+        }
+      }
+    });
+    double *dst = a.Q + (size_t)k * a.ldq;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+      const int i = r * RWG + tid;
+      if (i < a.m) {
+        coh_store(dst + i, q[r].re.h);
+        coh_store(dst + i + a.planeQ, q[r].im.h);
+        coh_store(dst + i + 2 * a.planeQ, q[r].re.l);
+        coh_store(dst + i + 3 * a.planeQ, q[r].im.l);
+      }
+    }
+    if (tid == 0) {
+      C d;
+      d.re = rkk;
+      d.im = P::rzero();
+      P::store(a.R + (size_t)k * a.ldr + k, a.planeR, d);
+    }
+    // Publish this wave's rows: its stores are complete (device-scope)
+    // before its counter moves.
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (lane == 0) __hip_atomic_store(a.sync + 16 * wave, (unsigned int)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+
+  __device__ __forceinline__ void copy_own(int k, C (&q)[RR]) {
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      if (cidx[s] == k) {
+#pragma unroll
+        for (int r = 0; r < RR; ++r) q[r] = col[s][r];
+      }
+    });
+  }
+  __device__ __forceinline__ void load_q(int k, C (&q)[RR]) {
+    const double *src = a.Q + (size_t)k * a.ldq;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+      const int i = r * RWG + tid;
+      q[r] = P::czero();
+      if (i < a.m) {
+        q[r].re.h = coh_load(src + i);
+        q[r].im.h = coh_load(src + i + a.planeQ);
+        q[r].re.l = coh_load(src + i + 2 * a.planeQ);
+        q[r].im.l = coh_load(src + i + 3 * a.planeQ);
+      }
+    }
+  }
+  __device__ __forceinline__ void spill_q(const C (&q)[RR]) {
+#pragma unroll
+    for (int r = 0; r < RR; ++r) P::store(qdef + (size_t)r * 2 * P::L * RWG + tid, (size_t)RWG, q[r]);
+  }
+  __device__ __forceinline__ void fill_q(C (&q)[RR]) {
+#pragma unroll
+    for (int r = 0; r < RR; ++r) q[r] = P::load(qdef + (size_t)r * 2 * P::L * RWG + tid, (size_t)RWG);
+  }
+
+  // Panel `i` of the owned list in ascending column order: [ps, pe).
+  __device__ __forceinline__ void panel(int i, int nq, int g, int &ps, int &pe) const {
+    if (i >= nq) {
+      ps = pe = RES_NONE;
+      return;
+    }
+    const int u = nq - 1 - i;
+    const int qi = 2 * a.G * (u / 2) + ((u & 1) ? 2 * a.G - 1 - g : g);
+    ps = (a.np - 1 - qi) * a.bw;
+    pe = ps + a.bw < a.ncols ? ps + a.bw : a.ncols;
+  }
+
+  // The whole schedule of one workgroup as a sequence of steps, each either
+  // a normalisation or one projection applied to a range of owned columns,
+  // so that the loop body holds a single copy of each (a small code
+  // footprint for the instruction cache).
+  __device__ void run() {
+    const int bid = blockIdx.x;
+    const int G = a.G;
+    const int g = a.xcd_group ? (bid % 8) * a.xcd_group + bid / 8 : bid;
+    // Owned panels: the i-th is q_i = 2G*(i/2) + (i even ? g : 2G-1-g) in
+    // reflected order, panel np-1-q_i; ascending columns = descending i.
+    int nq = 0;
+    while (true) {
+      const int qi = 2 * G * (nq / 2) + ((nq & 1) ? 2 * G - 1 - g : g);
+      if (qi >= a.np) break;
+      ++nq;
+    }
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      const int jp = s / a.bw, c = s - jp * a.bw;
+      int ps, pe;
+      panel(jp, nq, g, ps, pe);
+      cidx[s] = (ps != RES_NONE && ps + c < pe) ? ps + c : RES_NONE;
+    });
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      const int j = cidx[s];
+      const double *src = nullptr;
+      size_t pl = 0;
+      if (j < a.n) {
+        src = a.A + (size_t)j * a.lda;
+        pl = a.planeA;
+      } else if (j == a.n) {
+        src = a.b;
+        pl = (size_t)a.m;
+      }
+#pragma unroll
+      for (int r = 0; r < RR; ++r) {
+        const int i = r * RWG + tid;
+        col[s][r] = (src != nullptr && i < a.m) ? P::load(src + i, pl) : P::czero();
+      }
+    });
+    int last = -1;
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      if (cidx[s] != RES_NONE && cidx[s] > last) last = cidx[s];
+    });
+    if (last < 0) return;
+    const int kend = last < a.n ? last + 1 : a.n;
+
+    // States: 0 = projections from other workgroups, 1 = factoring an
+    // owned panel, 2 = deferred projections of that panel (and of the
+    // remote q that completed it) onto the later owned columns.
+    int st = 0, seen = 0, nxt = 0, k = 0;
+    int ps = 0, pe = 0, pa = 0, c = 0, kd = -1, dc = 0;
+    int qk = -1;  // q currently holds q_qk (this thread's rows)
+    bool need_norm = true;
+    C q[RR];
+    while (true) {
+      int opk = 0, lo = 0, hi = RES_NONE, src = 0;  // src: 0 remote, 1 owned, 2 LDS, 3 normalise
+      if (st == 0) {
+        if (k >= kend) break;
+        panel(nxt, nq, g, ps, pe);
+        if (k == ps) {
+          st = 1;
+          c = ps;
+          pa = pe < a.n ? pe : a.n;
+          need_norm = true;
+          kd = -1;
+          continue;
+        }
+        opk = k;
+        if (k + 1 == ps && ps < a.n) {
+          lo = ps;  // critical path first: the panel only
+          hi = pe;
+        } else {
+          lo = k + 1;
+        }
+      } else if (st == 1) {
+        opk = c;
+        if (need_norm) {
+          src = 3;
+        } else {
+          src = 1;
+          lo = c + 1;
+          hi = pe;
+        }
+      } else {
+        src = dc < 0 ? 2 : 1;
+        opk = dc < 0 ? kd : dc;
+        lo = pe;
+      }
+
+      if (src == 3) {
+        normalize(opk, q);
+      } else {
+        if (src == 0) {
+          if (!res_wait(a, opk, wave, seen)) return;
+          load_q(opk, q);
+        } else if (src == 1) {
+          if (qk != opk) copy_own(opk, q);
+        } else {
+          fill_q(q);
+        }
+        apply(q, opk, lo, hi);
+      }
+      qk = opk;
+
+      if (st == 0) {
+        if (hi != RES_NONE) {
+          spill_q(q);
+          kd = k;
+          st = 1;
+          c = ps;
+          pa = pe < a.n ? pe : a.n;
+          need_norm = true;
+        } else {
+          ++k;
+        }
+      } else if (st == 1) {
+        if (src == 3 && c + 1 < pe) {
+          need_norm = false;
+        } else {
+          ++c;
+          need_norm = true;
+          if (c >= pa) {
+            if (last >= pe) {
+              st = 2;
+              dc = kd >= 0 ? -1 : ps;
+            } else {
+              st = 0;
+              k = pe;
+              ++nxt;
+            }
+          }
+        }
+      } else {
+        dc = dc < 0 ? ps : dc + 1;
+        if (dc >= pa) {
+          st = 0;
+          k = pe;
+          ++nxt;
+        }
+      }
+    }
+
+    // rho = ||b - Q y|| after the last projection (Equation (1)).
+    if (a.rho != nullptr && last == a.n) {
+      copy_own(a.n, q);
+      Acc nacc;
+      P::acc_zero(nacc);
+#pragma unroll
+      for (int r = 0; r < RR; ++r) P::acc_abs2(nacc, q[r]);
+      wave_sum_dpp(nacc, true);
+      if (lane == 63) part[par][wave][0] = nacc;
+      lds_barrier();
+      const Acc t = merge_parts(0, true);
+      par ^= 1;
+      if (tid == 0) {
+        const Rl s2 = P::acc_value_re(t);
+        P::store_real(a.rho, 1, P::ok_norm(s2) ? P::sqrt_(s2) : P::rzero());
+      }
+    }
+    // Zeros below the diagonal of the owned columns of R.
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      const int j = cidx[s];
+      if (j < a.n) {
+        for (int i = j + 1 + tid; i < a.n; i += RWG) P::store(a.R + (size_t)j * a.ldr + i, a.planeR, P::czero());
+      }
+    });
+  }
+};
+
+template <class P, int RR, int CB, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4))) void mgs_resident_kernel(
+    ResArgs a) {
+  using Acc = typename P::Acc;
+  __shared__ Acc part[2][NW][CB];
+  __shared__ double qdef[RR * 2 * P::L * 64 * NW];
+  Resident<P, RR, CB, NW> st(a, part, qdef);
+  st.run();
+}
+
+// Clears the publication counters, the abort flag and (optionally) info
+// (one workgroup of RES_SYNC_WORDS threads).
+__global__ void resident_init_kernel(unsigned int *sync, int *info, int init_info) {
+  if (threadIdx.x < RES_SYNC_WORDS) sync[threadIdx.x] = 0u;
+  if (threadIdx.x == 0 && init_info) *info = 0;
+}
+
+}  // namespace mgsq

@@ -44,8 +44,9 @@ def test_status_strings():
 
 
 def test_workspace_sizes():
-    assert _lib.workspace_size(32, 32, 2, _lib.MGS_OP_QR) == 2 * 2 * 32 * 8
-    assert _lib.workspace_size(320, 256, 4, _lib.MGS_OP_QR) == 2 * 4 * 320 * 8
+    # QR: working copy of b (rounded to 256 bytes) + 1 KiB of sync words
+    assert _lib.workspace_size(32, 32, 2, _lib.MGS_OP_QR) == 2 * 2 * 32 * 8 + 1024
+    assert _lib.workspace_size(320, 256, 4, _lib.MGS_OP_QR) == 2 * 4 * 320 * 8 + 1024
     assert _lib.workspace_size(100, 10, 2, _lib.MGS_OP_SOLVE) == 512
     with pytest.raises(_lib.MgsError):
         _lib.workspace_size(10, 11, 2, _lib.MGS_OP_QR)
@@ -64,7 +65,7 @@ ODD = 0x10004 + 1
 
 
 def _qr(m=8, n=4, prec=2, A=FAKE, lda=8, Q=FAKE + 4096, ldq=8, R=FAKE + 8192, ldr=4, b=None, y=None,
-        rho=None, work=None, wb=0, info=FAKE + 12288):
+        rho=None, work=FAKE + 20480, wb=1 << 16, info=FAKE + 12288):
     return _lib.lib().mgs_qr(m, n, prec, A, lda, Q, ldq, R, ldr, b, y, rho, work, wb, info, None)
 
 
@@ -82,9 +83,11 @@ def test_mgs_qr_rejects_bad_arguments():
     assert _qr(A=ODD) == -2
     assert _qr(info=None) == -2
     assert _qr(Q=FAKE, A=FAKE, ldq=9, lda=8) in (-1, -2)
-    # b given: y and workspace required
-    assert _qr(b=FAKE + 16384, y=None, work=FAKE + 20480, wb=1024) == -2
-    assert _qr(b=FAKE + 16384, y=FAKE + 24576, work=None, wb=1024) == -2
+    # the workspace is always required; with b, y too
+    assert _qr(work=None) == -2
+    assert _qr(wb=8) == -4
+    assert _qr(b=FAKE + 16384, y=None, work=FAKE + 20480, wb=1 << 16) == -2
+    assert _qr(b=FAKE + 16384, y=FAKE + 24576, work=None, wb=1 << 16) == -2
     assert _qr(b=FAKE + 16384, y=FAKE + 24576, work=FAKE + 20480, wb=8) == -4
 
 

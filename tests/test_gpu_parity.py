@@ -5,7 +5,15 @@ Bar (dd / qd): err_Q, err_R (column relative) and err_x (equilibrated) below
 and the least-squares condition number for x.  Reductions run in a fixed
 order, so repeated runs are bitwise identical; exact scaling symmetries hold
 bitwise.
+
+Both schedules of the factorisation are checked on every random shape: the
+automatic choice (in dd the single cooperative launch whenever the columns
+fit in registers, m <= 1024) and the per-panel launches
+(MGSQR_SCHEDULE=panel).
 """
+import contextlib
+import os
+
 import numpy as np
 import pytest
 
@@ -31,9 +39,26 @@ def N(t):
     return None if t is None else t.cpu().numpy()
 
 
-def gpu_lstsq(A, b):
-    f = api.lstsq(T(A), T(b))
-    torch.cuda.synchronize()
+@contextlib.contextmanager
+def schedule(name):
+    old = os.environ.get("MGSQR_SCHEDULE")
+    if name == "auto":
+        os.environ.pop("MGSQR_SCHEDULE", None)
+    else:
+        os.environ["MGSQR_SCHEDULE"] = name
+    try:
+        yield
+    finally:
+        if old is None:
+            os.environ.pop("MGSQR_SCHEDULE", None)
+        else:
+            os.environ["MGSQR_SCHEDULE"] = old
+
+
+def gpu_lstsq(A, b, sched="auto"):
+    with schedule(sched):
+        f = api.lstsq(T(A), T(b))
+        torch.cuda.synchronize()
     return {k: N(v) for k, v in f.items()}
 
 
@@ -44,10 +69,17 @@ def oracle_lstsq(A, b):
     return o
 
 
-def check_case(A, b, prec, invariants=False):
-    g = gpu_lstsq(A, b)
+def check_case(A, b, prec, invariants=False, schedules=("auto",)):
     o = oracle_lstsq(A, b)
-    assert int(g["info"][0]) == 0 and o["info"] == 0
+    assert o["info"] == 0
+    for sched in schedules:
+        e, g = check_gpu(A, b, prec, o, invariants, sched)
+    return e, g, o
+
+
+def check_gpu(A, b, prec, o, invariants, sched):
+    g = gpu_lstsq(A, b, sched)
+    assert int(g["info"][0]) == 0, sched
     assert int(g["info_backsolve"][0]) == 0
     e = errors(A, g["Q"], g["R"], o["Q"], o["R"], g["x"], o["x"], o["rho"])
     assert_parity(e, prec)
@@ -69,7 +101,7 @@ def check_case(A, b, prec, invariants=False):
         m = A.shape[3]
         assert ev[1] <= 4 * m * EPS[prec], ev
         assert ev[2] <= 10 * e["kappa"] * n * EPS[prec], ev
-    return e, g, o
+    return e, g
 
 
 DD_SHAPES = [(1, 1), (5, 1), (32, 32), (33, 7), (64, 64), (65, 65), (100, 37), (200, 200), (257, 129),
@@ -80,13 +112,13 @@ QD_SHAPES = [(1, 1), (9, 3), (32, 32), (64, 20), (100, 100), (257, 40), (513, 30
 @pytest.mark.parametrize("m,n", DD_SHAPES)
 def test_dd_random_parity(m, n):
     p = inputs.random_problem(2, m, n, seed=m * 7 + n, config=50)
-    check_case(p["A"], p["b"], 2, invariants=(m * n <= 300 * 255))
+    check_case(p["A"], p["b"], 2, invariants=(m * n <= 300 * 255), schedules=("auto", "panel"))
 
 
 @pytest.mark.parametrize("m,n", QD_SHAPES)
 def test_qd_random_parity(m, n):
     p = inputs.random_problem(4, m, n, seed=m * 7 + n, config=51)
-    check_case(p["A"], p["b"], 4, invariants=(m * n <= 100 * 100))
+    check_case(p["A"], p["b"], 4, invariants=(m * n <= 100 * 100), schedules=("auto", "panel"))
 
 
 def test_config1_dd_32x32():
@@ -99,14 +131,14 @@ def test_config1_dd_32x32():
 
 def test_config2_qd_320x256():
     d = inputs.config2()
-    e, g, o = check_case(d["A"], d["b"], 4)
+    e, g, o = check_case(d["A"], d["b"], 4, schedules=("auto", "panel"))
     print("config2 parity", e)
 
 
 @pytest.mark.parametrize("system", [0, 63])
 def test_config3_dd_1024_jacobian(system):
     d = inputs.config3(system)
-    e, g, o = check_case(d["A"], d["b"], 2)
+    e, g, o = check_case(d["A"], d["b"], 2, schedules=("resident", "panel"))
     print("config3 system %d parity" % system, e)
 
 
@@ -157,8 +189,9 @@ def test_zero_column_and_zero_pivot_report_info():
     p = inputs.random_problem(2, 80, 40, seed=4, config=55)
     A = p["A"].copy()
     A[:, :, 17] = 0.0
-    g = gpu_lstsq(A, p["b"])
-    assert int(g["info"][0]) == 18
+    for sched in ("auto", "panel"):
+        g = gpu_lstsq(A, p["b"], sched)
+        assert int(g["info"][0]) == 18, sched
     R = np.zeros((2, 2, 5, 5))
     R[0, 0, np.arange(5), np.arange(5)] = [1, 2, 0, 4, 5]
     y = np.ones((2, 2, 5))
@@ -168,10 +201,11 @@ def test_zero_column_and_zero_pivot_report_info():
     assert int(info.item()) == 3
 
 
-def test_reproducible_bitwise():
+@pytest.mark.parametrize("sched", ["auto", "panel"])
+def test_reproducible_bitwise(sched):
     p = inputs.random_problem(2, 700, 400, seed=5, config=56)
-    g1 = gpu_lstsq(p["A"], p["b"])
-    g2 = gpu_lstsq(p["A"], p["b"])
+    g1 = gpu_lstsq(p["A"], p["b"], sched)
+    g2 = gpu_lstsq(p["A"], p["b"], sched)
     for k in ("Q", "R", "y", "rho", "x"):
         assert np.array_equal(g1[k], g2[k]), k
 
