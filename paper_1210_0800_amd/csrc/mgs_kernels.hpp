@@ -419,30 +419,61 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 
 // ------------------------------------------------- back substitution -----
 // Section 6, Figure 3: for k = n..1, x_k = y_k / r_kk, then y_j -= r_jk x_k
-// for all j < k in parallel.  One block; thread tid keeps y_j for
-// j = s*WG + tid in registers; the reciprocals of the diagonal are formed
-// in parallel up front, so the serial chain per step is one product, one
-// LDS broadcast (double-buffered: one barrier per step) and one update.
+// for all j < k.  The reciprocals of the diagonal are formed in parallel up
+// front.
+// Blocked form of the same back substitution: one workgroup of BS_T
+// threads, thread t holding y_j for j = s*BS_T + t.  The columns are taken
+// in blocks [k0, k0 + BS_B) from the bottom.  For each block:
+//   1. its upper triangle of R is staged in LDS;
+//   2. the one wave that holds rows k0 .. k0+BS_B-1 solves the block:
+//      x_k = y_k / r_kk (owner lane), x_k broadcast by readlane, then
+//      y_j -= r_jk x_k for the block rows j < k;
+//   3. every thread with a row j < k0 applies y_j -= r_jk x_k for the
+//      block's k in descending order (R read from global, coalesced).
+// Each y_j still receives r_jk x_k in the order k = n, n-1, ..., j+1 of
+// Figure 3 with the same operations, so x is bitwise that of the
+// column-oriented loop; the serial chain is BS_B readlane steps per block
+// instead of one block barrier per column.
+constexpr int BS_T = 1024;
+constexpr int BS_B = 32;
+
+template <class P>
+__device__ __forceinline__ typename P::C bs_readlane(const typename P::C &v, int lane) {
+  typename P::C r;
+  double *pr = reinterpret_cast<double *>(&r);
+  const double *pv = reinterpret_cast<const double *>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(typename P::C) / sizeof(double)); ++i) {
+    const long long b = __double_as_longlong(pv[i]);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    pr[i] = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+  return r;
+}
+
 template <class P, int NY>
-__global__ __launch_bounds__(WG) void backsolve_kernel(int n, const double *R, int ldr, size_t planeR,
-                                                        const double *y, size_t planeY, double *x, int *info,
-                                                        const int *skip) {
+__global__ __launch_bounds__(BS_T) void backsolve_blocked_kernel(int n, const double *R, int ldr, size_t planeR,
+                                                                  const double *y, size_t planeY, double *x,
+                                                                  int *info, const int *skip) {
   if (skip != nullptr && *skip != 0) return;
   using C = typename P::C;
   using Rl = typename P::R;
-  __shared__ C xs[2];
+  constexpr int NP = 2 * P::L;  // planes of a complex element
+  __shared__ double rb[NP * BS_B * BS_B];  // block of R, planar [p][col][row]
+  __shared__ double xs[NP * BS_B];         // x of the block, planar [p][k]
   __shared__ int bad;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   if (tid == 0) bad = 0x7fffffff;
   __syncthreads();
   C yv[NY];
   Rl inv[NY];
 #pragma unroll
   for (int s = 0; s < NY; ++s) {
-    int j = s * WG + tid;
+    const int j = s * BS_T + tid;
     if (j < n) {
       yv[s] = P::load(y + j, planeY);
-      C d = P::load(R + (size_t)j * ldr + j, planeR);
+      const C d = P::load(R + (size_t)j * ldr + j, planeR);
       if (!P::ok_norm(d.re)) atomicMin(&bad, j + 1);
       inv[s] = P::recip(d.re);
     } else {
@@ -452,27 +483,54 @@ __global__ __launch_bounds__(WG) void backsolve_kernel(int n, const double *R, i
   }
   __syncthreads();
   if (tid == 0 && info != nullptr) *info = (bad == 0x7fffffff) ? 0 : bad;
+  const int nblk = (n + BS_B - 1) / BS_B;
 #pragma unroll 1
-  for (int k = n - 1; k >= 0; --k) {
-    const int sk = k / WG, owner = k - sk * WG;
-    if (tid == owner) {
+  for (int kb = nblk - 1; kb >= 0; --kb) {
+    const int k0 = kb * BS_B;
+    const int k1 = k0 + BS_B < n ? k0 + BS_B : n;
+    const int nb = k1 - k0;
+    // 1. R(k0 + r, k0 + c) for r <= c < nb into LDS.
+    for (int e = tid; e < BS_B * BS_B; e += BS_T) {
+      const int c = e / BS_B, r = e - c * BS_B;
+      if (c < nb && r <= c) {
+        const C v = P::load(R + (size_t)(k0 + c) * ldr + (k0 + r), planeR);
+        P::store(rb + c * BS_B + r, (size_t)BS_B * BS_B, v);
+      }
+    }
+    __syncthreads();
+    // 2. The wave holding rows k0 .. k1-1 (one slot s, consecutive lanes).
+    const int sk = k0 / BS_T, tk = k0 - sk * BS_T;
+    if (wave == tk / 64) {
+      const int l0 = tk % 64;
 #pragma unroll
       for (int s = 0; s < NY; ++s) {
         if (s == sk) {
-          C xk = P::scale(yv[s], inv[s]);
-          P::store(x + k, (size_t)n, xk);
-          xs[k & 1] = xk;
+          const int i = lane - l0;  // block row of this lane
+#pragma unroll 1
+          for (int c = nb - 1; c >= 0; --c) {
+            const C xl = P::scale(yv[s], inv[s]);
+            const C xk = bs_readlane<P>(xl, l0 + c);
+            if (i == c) {
+              P::store(x + k0 + c, (size_t)n, xk);
+              P::store(xs + c, (size_t)BS_B, xk);
+            }
+            if (i >= 0 && i < c) P::upd(yv[s], P::load(rb + c * BS_B + i, (size_t)BS_B * BS_B), xk);
+          }
         }
       }
     }
     __syncthreads();
-    const C xk = xs[k & 1];
-    const double *Rk = R + (size_t)k * ldr;
+    // 3. Rows above the block.
 #pragma unroll
     for (int s = 0; s < NY; ++s) {
-      int j = s * WG + tid;
-      if (s <= sk && j < k) P::upd(yv[s], P::load(Rk + j, planeR), xk);
+      const int j = s * BS_T + tid;
+      if (j < k0) {
+#pragma unroll 4
+        for (int c = nb - 1; c >= 0; --c)
+          P::upd(yv[s], P::load(R + (size_t)(k0 + c) * ldr + j, planeR), P::load(xs + c, (size_t)BS_B));
+      }
     }
+    __syncthreads();
   }
 }
 

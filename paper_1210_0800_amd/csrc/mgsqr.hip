@@ -137,20 +137,18 @@ int dispatch_shape(const StepArgs &a, const Shape &sh, hipStream_t st) {
 template <class P>
 int backsolve_launch(int n, const double *R, int ldr, const double *y, double *x, int *info, hipStream_t st,
                      size_t planeR = 0, const int *skip = nullptr, size_t planeY = 0) {
-  const int ny = pow2_at_least(ceil_div(n, WG));
+  const int ny = pow2_at_least(ceil_div(n, BS_T));
   if (planeR == 0) planeR = (size_t)ldr * n;
   if (planeY == 0) planeY = (size_t)n;
 #define MGS_NY_CASE(NYV)                                                                                    \
   case NYV:                                                                                                 \
-    hipLaunchKernelGGL((backsolve_kernel<P, NYV>), dim3(1), dim3(WG), 0, st, n, R, ldr, planeR, y, planeY,    \
-                       x, info, skip);                                                                      \
+    hipLaunchKernelGGL((backsolve_blocked_kernel<P, NYV>), dim3(1), dim3(BS_T), 0, st, n, R, ldr, planeR, y, \
+                       planeY, x, info, skip);                                                              \
     break;
   switch (ny) {
     MGS_NY_CASE(1)
     MGS_NY_CASE(2)
     MGS_NY_CASE(4)
-    MGS_NY_CASE(8)
-    MGS_NY_CASE(16)
     default:
       return MGS_ERR_DIMS;
   }
@@ -466,6 +464,7 @@ int res_launch_dd(const StepArgs &s, void *sync, hipStream_t st) {
   a.np = pl.np;
   a.G = pl.G;
   a.xcd_group = pl.G % 8 == 0 ? pl.G / 8 : 0;
+  a.defer = 2;
   a.spin_ticks = d.wclk_khz * 2000;  // 2 s
   switch (pl.rr) {
     case 1: return res_launch_rr<P, 1>(a, d.cus, st);

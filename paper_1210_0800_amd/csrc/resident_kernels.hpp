@@ -28,10 +28,12 @@
 //    needs a workgroup barrier, an L2 write-back or an L2 invalidation.
 //    Publication is in the order k = 0, 1, ..., so one counter per wave
 //    covers every column.
-//  * Critical path first: when the q that completes a workgroup's next
-//    panel arrives, it is applied to that panel only, the panel is factored
-//    and published, and only then are the deferred projections applied to
-//    the workgroup's later columns (still in the order k, k+1, ...).
+//  * Critical path first: once the factorisation front is within `defer`
+//    columns of a workgroup's next panel, the arriving q vectors are
+//    applied to that panel only; the panel is factored and published, and
+//    only then do the workgroup's later columns receive the deferred
+//    projections (re-read from Q) and the panel's own, in the order k,
+//    k+1, ...
 //  * Consecutive panels sit on the same XCD (workgroup numbering is
 //    rotated so that logical workgroups 0..G/8-1 land on one XCD), so most
 //    hand-offs stay inside one L2.
@@ -63,6 +65,7 @@ struct ResArgs {
   unsigned int *sync;  // RES_SYNC_WORDS words, zero at launch: per-wave counters and the abort flag
   int bw, np, G;
   int xcd_group;        // logical workgroups per XCD (G / 8), 0 for identity numbering
+  int defer;            // look-ahead window of the critical-path-first rule (columns)
   long long spin_ticks;  // wall-clock limit of one wait
 };
 
@@ -156,11 +159,9 @@ struct Resident {
   int cidx[CB];  // column of each slot, ascending; RES_NONE when empty
   C col[CB][RR];
   Acc (*part)[NW][CB];     // LDS: [2][NW][CB] partial sums
-  double *qdef;            // LDS: thread-private spill of a deferred q
   int par;
 
-  __device__ __forceinline__ Resident(const ResArgs &args, Acc (*p)[NW][CB], double *qd)
-      : a(args), part(p), qdef(qd), par(0) {
+  __device__ __forceinline__ Resident(const ResArgs &args, Acc (*p)[NW][CB]) : a(args), part(p), par(0) {
     tid = threadIdx.x;
     wave = tid >> 6;
     lane = tid & 63;
@@ -302,15 +303,6 @@ struct Resident {
       }
     }
   }
-  __device__ __forceinline__ void spill_q(const C (&q)[RR]) {
-#pragma unroll
-    for (int r = 0; r < RR; ++r) P::store(qdef + (size_t)r * 2 * P::L * RWG + tid, (size_t)RWG, q[r]);
-  }
-  __device__ __forceinline__ void fill_q(C (&q)[RR]) {
-#pragma unroll
-    for (int r = 0; r < RR; ++r) q[r] = P::load(qdef + (size_t)r * 2 * P::L * RWG + tid, (size_t)RWG);
-  }
-
   // Panel `i` of the owned list in ascending column order: [ps, pe).
   __device__ __forceinline__ void panel(int i, int nq, int g, int &ps, int &pe) const {
     if (i >= nq) {
@@ -373,15 +365,15 @@ struct Resident {
     const int kend = last < a.n ? last + 1 : a.n;
 
     // States: 0 = projections from other workgroups, 1 = factoring an
-    // owned panel, 2 = deferred projections of that panel (and of the
-    // remote q that completed it) onto the later owned columns.
+    // owned panel, 2 = deferred projections (remote q_kd .. q_{ps-1}, then
+    // the panel's own) onto the later owned columns.
     int st = 0, seen = 0, nxt = 0, k = 0;
     int ps = 0, pe = 0, pa = 0, c = 0, kd = -1, dc = 0;
     int qk = -1;  // q currently holds q_qk (this thread's rows)
     bool need_norm = true;
     C q[RR];
     while (true) {
-      int opk = 0, lo = 0, hi = RES_NONE, src = 0;  // src: 0 remote, 1 owned, 2 LDS, 3 normalise
+      int opk = 0, lo = 0, hi = RES_NONE, src = 0;  // src: 0 remote, 1 owned, 2 published earlier, 3 normalise
       if (st == 0) {
         if (k >= kend) break;
         panel(nxt, nq, g, ps, pe);
@@ -390,13 +382,13 @@ struct Resident {
           c = ps;
           pa = pe < a.n ? pe : a.n;
           need_norm = true;
-          kd = -1;
           continue;
         }
         opk = k;
-        if (k + 1 == ps && ps < a.n) {
+        if (ps < a.n && k + a.defer >= ps) {
           lo = ps;  // critical path first: the panel only
           hi = pe;
+          if (kd < 0) kd = k;
         } else {
           lo = k + 1;
         }
@@ -410,8 +402,8 @@ struct Resident {
           hi = pe;
         }
       } else {
-        src = dc < 0 ? 2 : 1;
-        opk = dc < 0 ? kd : dc;
+        src = dc < ps ? 2 : 1;
+        opk = dc;
         lo = pe;
       }
 
@@ -424,22 +416,19 @@ struct Resident {
         } else if (src == 1) {
           if (qk != opk) copy_own(opk, q);
         } else {
-          fill_q(q);
+          load_q(opk, q);  // this wave has already seen it published
         }
         apply(q, opk, lo, hi);
       }
       qk = opk;
 
       if (st == 0) {
-        if (hi != RES_NONE) {
-          spill_q(q);
-          kd = k;
+        ++k;
+        if (k == ps && ps < a.n) {
           st = 1;
           c = ps;
           pa = pe < a.n ? pe : a.n;
           need_norm = true;
-        } else {
-          ++k;
         }
       } else if (st == 1) {
         if (src == 3 && c + 1 < pe) {
@@ -450,20 +439,22 @@ struct Resident {
           if (c >= pa) {
             if (last >= pe) {
               st = 2;
-              dc = kd >= 0 ? -1 : ps;
+              dc = kd >= 0 ? kd : ps;
             } else {
               st = 0;
               k = pe;
               ++nxt;
+              kd = -1;
             }
           }
         }
       } else {
-        dc = dc < 0 ? ps : dc + 1;
+        ++dc;
         if (dc >= pa) {
           st = 0;
           k = pe;
           ++nxt;
+          kd = -1;
         }
       }
     }
@@ -501,8 +492,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
     ResArgs a) {
   using Acc = typename P::Acc;
   __shared__ Acc part[2][NW][CB];
-  __shared__ double qdef[RR * 2 * P::L * 64 * NW];
-  Resident<P, RR, CB, NW> st(a, part, qdef);
+  Resident<P, RR, CB, NW> st(a, part);
   st.run();
 }
 
