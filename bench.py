@@ -7,7 +7,13 @@ on [A b] (mgs_qr) then back substitution (ls_backsolve).  Inputs are
 resident in HBM before the timed region.
 
 Prints one JSON line: solves/s, the roofline of the dominant kernel sequence
-(the MGS factorisation, FP64 vector ALU bound) and the CPU oracle baseline.
+(the MGS factorisation, FP64 vector ALU bound), the CPU oracle baseline and
+the precision form measured against plain MGS at equal error on the
+2048 x 2048, kappa = 1e10 workload (time, error against x_true, iterations,
+in dd and qd).
+
+--copy-probe BYTES only copies a device buffer of that size (for scaling the
+HBM counters of a profiler run) and exits.
 """
 import argparse
 import json
@@ -26,6 +32,28 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 # FP64 flops per operation of the dd kernels (FMA = 2), counted from the
 # formulations in paper_1210_0800_amd/csrc/ddqd.hpp.
 F_DD = dict(cmulc=60, upd=66, abs2=28, scale=20, merge=16)
+
+
+# HBM bytes per launch of the resident factorisation kernel (dd 1024 x 1024
+# with b), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this
+# benchmark, each scaled by the same counter on a device copy of known size
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0; see profiles/).  Valid only for the
+# kernel sources they were taken on (hash below); reported as null otherwise.
+TRAFFIC = dict(fetch_bytes=2.0 * 121436.3 * 1024, write_bytes=65959.7 * 1024, sources="1d197c06fbef29f1")
+KERNEL_SOURCES = ["paper_1210_0800_amd/csrc/resident_kernels.hpp", "paper_1210_0800_amd/csrc/ddqd.hpp",
+                  "paper_1210_0800_amd/csrc/mgs_kernels.hpp"]
+
+
+def traffic_bytes():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != TRAFFIC["sources"]:
+        return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 
 
 def mgs_flops(m, n, ncols, F=F_DD):
@@ -76,6 +104,76 @@ def cpu_baseline(inputs_np, budget_s=20.0):
                 (done, dt))
 
 
+def _exact_rel_err(x, x_true):
+    """||x - x_true|| / ||x_true|| with the differences formed exactly
+    (limb sums as rationals), then rounded to FP64."""
+    from fractions import Fraction
+
+    def vals(X):
+        Xs = X.reshape(X.shape[0], -1)
+        return [sum(Fraction(float(v)) for v in Xs[:, i]) for i in range(Xs.shape[1])]
+
+    a, t = vals(x), vals(x_true)
+    num = sum(float(u - v) ** 2 for u, v in zip(a, t))
+    den = sum(float(v) ** 2 for v in t)
+    return (num / den) ** 0.5
+
+
+def precision_form(torch, api, n=2048, reps=2):
+    """Refined (FP64 blocked MGS + dd/qd refinement) vs plain dd/qd MGS on
+    A = U diag(sigma) V^H, kappa 1e10, b the exact product A x_true rounded
+    to qd: time of each, relative error against x_true, iterations."""
+    from paper_1210_0800_amd import inputs
+
+    t_gen = time.perf_counter()
+    d = inputs.config4(n, workers=min(16, len(os.sched_getaffinity(0))))
+    t_gen = time.perf_counter() - t_gen
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    out = {"workload": "complex %dx%d A = U diag(sigma) V^H (4+4 Householder reflectors, sigma log-spaced, "
+                       "kappa 1e10), b = A x_true exactly rounded to qd" % (n, n),
+           "inputs_s": t_gen}
+    for L, name in ((2, "dd"), (4, "qd")):
+        A = np.zeros((L,) + d["A64"].shape[1:])
+        A[0] = d["A64"][0]
+        At = torch.from_numpy(A).to(dev)
+        bt = torch.from_numpy(np.ascontiguousarray(d["b4"][:L])).to(dev)
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                r = fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return r, e0.elapsed_time(e1) / reps
+
+        fp, tp = timed(lambda: api.lstsq(At, bt))
+        fr, tr = timed(lambda: api.refine_lstsq(At, bt, max_iter=30))
+        ep = _exact_rel_err(fp["x"].cpu().numpy(), d["x_true"])
+        er = _exact_rel_err(fr["x"].cpu().numpy(), d["x_true"])
+        out[name] = {"plain_ms": tp, "refined_ms": tr, "plain_err": ep, "refined_err": er,
+                     "iters": int(fr["iters"].item()), "info": int(fr["info"].item()),
+                     "speedup": tp / tr, "refined_reaches_plain_error": er <= ep,
+                     "refined_within_10x_plain_error": er <= 10 * ep}
+        print("bench: precision form %s plain %.1f ms err %.2e | refined %.1f ms err %.2e iters %d" %
+              (name, tp, ep, tr, er, out[name]["iters"]), file=sys.stderr, flush=True)
+    return out
+
+
+def copy_probe(nbytes):
+    import torch
+
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("bench: copied %d bytes 3 times" % nbytes, file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,7 +181,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--systems", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-form", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0)
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
@@ -173,10 +276,13 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": traffic_bytes(),
             "flops_per_solve": f_qr,
+            "algorithmic_bytes": 16 * 2 * (m * n + m + m * n + n * n + n),
         },
     }
+    if not args.no_precision_form:
+        out["precision_form"] = precision_form(torch, api)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host[:4])
     print(json.dumps(out), flush=True)
