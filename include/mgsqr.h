@@ -64,7 +64,7 @@ enum {
 /* *info value of a factorisation whose inter-workgroup wait timed out. */
 #define MGS_INFO_SYNC_TIMEOUT (-9)
 
-enum { MGS_OP_QR = 0, MGS_OP_SOLVE = 1, MGS_OP_ADJOINT = 2, MGS_OP_REFINE = 3 };
+enum { MGS_OP_QR = 0, MGS_OP_SOLVE = 1, MGS_OP_ADJOINT = 2, MGS_OP_REFINE = 3, MGS_OP_QR64 = 4 };
 
 /* Largest supported row count m: dd 4096, qd 2048. */
 #define MGS_MAX_ROWS_DD 4096
@@ -74,7 +74,8 @@ int mgs_abi_version(void);
 const char *mgs_status_string(int status);
 
 /* Bytes of device workspace needed by operation `op` (MGS_OP_QR,
- * MGS_OP_SOLVE, MGS_OP_ADJOINT, MGS_OP_REFINE) for an m x n problem;
+ * MGS_OP_SOLVE, MGS_OP_ADJOINT, MGS_OP_REFINE with prec 2 or 4;
+ * MGS_OP_QR64 with prec 1) for an m x n problem;
  * written to *bytes.  A workspace may be reused by later calls on the same
  * stream; calls that may overlap need distinct workspaces. */
 int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
@@ -182,6 +183,30 @@ int ls_adjoint(int m, int n, int prec, const double *A, int lda, const double *b
 int mgs_refine_solve(int m, int n, int prec, const double *A, int lda, const double *b, double *x, int block,
                      double tol, int max_iter, int *iters, double *err_est, void *work, size_t work_bytes, int *info,
                      mgs_stream_t stream);
+
+/*
+ * mgs_qr64 -- the factorisation of the precision form on its own: complex
+ * FP64 blocked MGS of [A b] (not in the paper, whose Section 2 leaves
+ * blocked versions aside).  For each panel of `block` columns, the MGS of
+ * Figure 1 inside the panel (FP64 vector units), then W = Q_p^H A_t and
+ * A_t -= Q_p W for the trailing columns A_t (b included) as complex
+ * products on the FP64 matrix cores.  Every column receives the panels'
+ * projections in panel order.
+ *   A  [in]   m x n complex FP64 planar: 2 planes (re, im) of lda x n
+ *             column-major doubles, lda >= m.
+ *   b  [in]   m complex FP64 planar (2 planes of m) or NULL.
+ *   Q  [out]  m x n planar (ldq >= m); R [out] n x n planar (ldr >= n),
+ *             upper triangular, real positive diagonal, lower triangle 0.
+ *   y  [out]  n planar: y = Q^H b as the projections of b (required when
+ *             b != NULL, ignored otherwise).
+ *   block     panel width; must be 64.
+ *   work      mgs_workspace_size(m, n, 1, MGS_OP_QR64, .) bytes.
+ *   info      device int: 0, or k > 0 when column k had a zero or
+ *             non-finite norm.
+ * Requires 1 <= n <= m <= MGS_MAX_ROWS_DD.
+ */
+int mgs_qr64(int m, int n, const double *A, int lda, const double *b, double *Q, int ldq, double *R, int ldr,
+             double *y, int block, void *work, size_t work_bytes, int *info, mgs_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -15,10 +15,11 @@ MGS_OP_QR = 0
 MGS_OP_SOLVE = 1
 MGS_OP_ADJOINT = 2
 MGS_OP_REFINE = 3
+MGS_OP_QR64 = 4
 MGS_MAX_ROWS = {2: 4096, 4: 2048}
 
 EXPORTS = ("mgs_abi_version", "mgs_status_string", "mgs_workspace_size", "mgs_qr", "ls_solve",
-           "ls_backsolve", "ls_adjoint", "mgs_refine_solve")
+           "ls_backsolve", "ls_adjoint", "mgs_refine_solve", "mgs_qr64")
 
 _lib = None
 
@@ -54,6 +55,8 @@ def lib():
         L.ls_adjoint.restype = I
         L.mgs_refine_solve.argtypes = [I, I, I, P, I, P, P, I, ctypes.c_double, I, P, P, P, S, P, P]
         L.mgs_refine_solve.restype = I
+        L.mgs_qr64.argtypes = [I, I, P, I, P, P, I, P, I, P, I, P, S, P, P]
+        L.mgs_qr64.restype = I
         _lib = L
     return _lib
 

@@ -125,6 +125,33 @@ def ls_adjoint(A, b, Q, R, x, gx, *, gA=None, gb=None, info=None, work=None):
     return gA, gb, info
 
 
+def mgs_qr64(A, b=None, *, block=64):
+    """FP64 complex blocked MGS of [A b] (the precision form's factorisation).
+
+    A: float64 [2, n, m] planar (re, im) on a HIP device, b: [2, m] or None.
+    Returns dict(Q, R, y, info).
+    """
+    if not isinstance(A, torch.Tensor) or A.dtype != torch.float64 or not A.is_contiguous() or not A.is_cuda:
+        raise ValueError("A must be a contiguous float64 tensor on a HIP device")
+    if A.dim() != 3 or A.shape[0] != 2:
+        raise ValueError("A must have shape [2, n, m], got %s" % (tuple(A.shape),))
+    _, n, m = A.shape
+    dev = A.device
+    if b is not None:
+        if not isinstance(b, torch.Tensor) or b.dtype != torch.float64 or not b.is_contiguous() or not b.is_cuda \
+                or tuple(b.shape) != (2, m):
+            raise ValueError("b must be a contiguous float64 [2, m] tensor on the device of A")
+    Q = torch.empty_like(A)
+    R = torch.empty((2, n, n), dtype=torch.float64, device=dev)
+    y = torch.empty((2, n), dtype=torch.float64, device=dev) if b is not None else None
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    work = workspace(m, n, 1, _lib.MGS_OP_QR64, dev)
+    st = _lib.lib().mgs_qr64(m, n, _ptr(A), m, _ptr(b), _ptr(Q), m, _ptr(R), n, _ptr(y), block, _ptr(work),
+                             work.numel() * 8, _ptr(info), _stream(A))
+    _lib.check("mgs_qr64", st)
+    return dict(Q=Q, R=R, y=y, info=info)
+
+
 def refine_lstsq(A, b, *, tol=None, max_iter=20, x=None, work=None):
     """Precision form: FP64 blocked-MGS factorisation (panels of 64, trailing
     products on matrix cores) and dd / qd iterative refinement of x.

@@ -255,6 +255,11 @@ RefineWork refine_layout(int m, int n, int prec, void *base) {
   return w;
 }
 
+// mgs_qr64: Q64 (m x (n+1)) and R64 (n x (n+1)), FP64 complex.
+size_t qr64_work_bytes(int m, int n) {
+  return round256(sizeof(double) * 2 * (size_t)m * (n + 1)) + round256(sizeof(double) * 2 * (size_t)n * (n + 1));
+}
+
 // FP64 blocked MGS of [A64 b64] held in Q64 (m x (n+1)); R64 (n x (n+1))
 // receives R and, in its last column, y.
 int factor64(int m, int n, const RefineWork &w, int *info, hipStream_t st) {
@@ -504,14 +509,15 @@ const char *mgs_status_string(int status) {
 }
 
 int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes) {
-  if (prec != 2 && prec != 4) return MGS_ERR_PREC;
-  if (n < 1 || m < n || m > max_rows(prec)) return MGS_ERR_DIMS;
+  if (op == MGS_OP_QR64 ? prec != 1 : (prec != 2 && prec != 4)) return MGS_ERR_PREC;
+  if (n < 1 || m < n || m > (op == MGS_OP_QR64 ? MGS_MAX_ROWS_DD : max_rows(prec))) return MGS_ERR_DIMS;
   if (!bytes) return MGS_ERR_POINTER;
   switch (op) {
     case MGS_OP_QR: *bytes = qr_work_bytes(m, prec); return MGS_OK;
     case MGS_OP_SOLVE: *bytes = solve_work_bytes(n, prec); return MGS_OK;
     case MGS_OP_ADJOINT: *bytes = adjoint_work_bytes(m, n, prec); return MGS_OK;
     case MGS_OP_REFINE: *bytes = refine_layout(m, n, prec, nullptr).bytes; return MGS_OK;
+    case MGS_OP_QR64: *bytes = qr64_work_bytes(m, n); return MGS_OK;
   }
   return MGS_ERR_UNSUPPORTED;
 }
@@ -616,6 +622,27 @@ int mgs_refine_solve(int m, int n, int prec, const double *A, int lda, const dou
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (prec == 2) return refine_solve<PrecDD>(m, n, A, lda, b, x, tol, max_iter, iters, err_est, work, info, st);
   return refine_solve<PrecQD>(m, n, A, lda, b, x, tol, max_iter, iters, err_est, work, info, st);
+}
+
+int mgs_qr64(int m, int n, const double *A, int lda, const double *b, double *Q, int ldq, double *R, int ldr,
+             double *y, int block, void *work, size_t work_bytes, int *info, mgs_stream_t stream) {
+  if (block != NBP) return MGS_ERR_PREC;
+  if (n < 1 || m < n || m > MGS_MAX_ROWS_DD || lda < m || ldq < m || ldr < n) return MGS_ERR_DIMS;
+  if (!aligned8(A) || !aligned8(Q) || !aligned8(R) || !aligned8(info) || !aligned8(work)) return MGS_ERR_POINTER;
+  if (b != nullptr && (!aligned8(b) || !aligned8(y))) return MGS_ERR_POINTER;
+  if (work_bytes < qr64_work_bytes(m, n)) return MGS_ERR_WORKSPACE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  RefineWork w;
+  w.Q64 = static_cast<double *>(work);
+  w.R64 = reinterpret_cast<double *>(static_cast<char *>(work) + round256(sizeof(double) * 2 * (size_t)m * (n + 1)));
+  hipLaunchKernelGGL(copy64_in_kernel, dim3(ceil_div(m, 256), n + 1), dim3(256), 0, st, m, n, A, lda, b, w.Q64, info);
+  if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
+  const int rc = factor64(m, n, w, info, st);
+  if (rc != MGS_OK) return rc;
+  const int gx = ceil_div(m, 256) < 4 ? ceil_div(m, 256) : 4;
+  hipLaunchKernelGGL(copy64_out_kernel, dim3(gx, n + 1), dim3(256), 0, st, m, n, w.Q64, w.R64, Q, ldq, R, ldr,
+                     b != nullptr ? y : nullptr);
+  return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
 }
 
 }  // extern "C"

@@ -150,6 +150,48 @@ __global__ __launch_bounds__(256) void copy_hi_kernel(int m, int n, const double
   }
 }
 
+// mgs_qr64: [A b] (FP64 complex planar, lda) into the working matrix
+// Q64 (m x (n+1), column n = b or zero); clears info.
+__global__ __launch_bounds__(256) void copy64_in_kernel(int m, int n, const double *A, int lda, const double *b,
+                                                         double *Q64, int *info) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (blockIdx.x == 0 && j == 0 && threadIdx.x == 0) *info = 0;
+  if (i >= m) return;
+  const size_t plane64 = (size_t)m * (n + 1);
+  if (j < n) {
+    const size_t planeA = (size_t)lda * n;
+    Q64[(size_t)j * m + i] = A[(size_t)j * lda + i];
+    Q64[(size_t)j * m + i + plane64] = A[(size_t)j * lda + i + planeA];
+  } else {
+    Q64[(size_t)n * m + i] = b != nullptr ? b[i] : 0.0;
+    Q64[(size_t)n * m + i + plane64] = b != nullptr ? b[i + m] : 0.0;
+  }
+}
+// mgs_qr64: Q (m x n, ldq), R (n x n, ldr) and y (n) out of Q64 / R64.
+// Block column j < n copies column j of Q and of R; j == n copies y.
+__global__ __launch_bounds__(256) void copy64_out_kernel(int m, int n, const double *Q64, const double *R64,
+                                                          double *Q, int ldq, double *R, int ldr, double *y) {
+  const int j = blockIdx.y;
+  const size_t plane64 = (size_t)m * (n + 1), planeR64 = (size_t)n * (n + 1);
+  if (j < n) {
+    const size_t planeQ = (size_t)ldq * n, planeR = (size_t)ldr * n;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256) {
+      Q[(size_t)j * ldq + i] = Q64[(size_t)j * m + i];
+      Q[(size_t)j * ldq + i + planeQ] = Q64[(size_t)j * m + i + plane64];
+    }
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+      R[(size_t)j * ldr + i] = R64[(size_t)j * n + i];
+      R[(size_t)j * ldr + i + planeR] = R64[(size_t)j * n + i + planeR64];
+    }
+  } else if (y != nullptr) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+      y[i] = R64[(size_t)n * n + i];
+      y[i + n] = R64[(size_t)n * n + i + planeR64];
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void fill_zero_kernel(double *p, size_t count) {
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) p[i] = 0.0;
 }

@@ -67,7 +67,9 @@ def errors(A, Qg, Rg, Qo, Ro, xg=None, xo=None, rho=None):
     return out
 
 
-TAU = {2: 1e-28, 4: 1e-58}
+# Parity bars per precision: about 2^12 units of the working precision
+# (FP64 2^-53, dd 2^-104, qd 2^-209), times max(1, kappa / 100) at use.
+TAU = {1: 5e-13, 2: 1e-28, 4: 1e-58}
 
 
 def assert_parity(e, prec, what=("err_q", "err_r", "err_x")):

@@ -133,3 +133,30 @@ def test_ls_adjoint_rejects_bad_arguments():
     assert call(gb=FAKE + 64) == -2   # aliases b
     assert call(wb=16) == -4
     assert _lib.workspace_size(8, 4, 2, _lib.MGS_OP_ADJOINT) == 3 * 256
+
+
+def test_mgs_qr64_rejects_bad_arguments():
+    L = _lib.lib()
+    names = ["m", "n", "A", "lda", "b", "Q", "ldq", "R", "ldr", "y", "block", "work", "wb", "info", "stream"]
+    args = [8, 4, FAKE, 8, FAKE + 128, FAKE + 256, 8, FAKE + 512, 4, FAKE + 1024, 64, FAKE + 2048, 1 << 20,
+            FAKE + 4096, None]
+
+    def call(**kw):
+        a = list(args)
+        for k, v in kw.items():
+            a[names.index(k)] = v
+        return L.mgs_qr64(*a)
+    assert call(block=32) == -3
+    assert call(m=3) == -1
+    assert call(m=4097, lda=4097, ldq=4097) == -1
+    assert call(ldr=3) == -1
+    assert call(A=None) == -2
+    assert call(y=None) == -2          # b given, y required
+    assert call(work=None) == -2
+    assert call(wb=64) == -4
+    # b == NULL: y may be NULL (fails later on the workspace, not the pointer)
+    assert call(b=None, y=None, wb=64) == -4
+    # Q64 (8 x 5) and R64 (4 x 5) complex FP64, each rounded up to 256 bytes
+    assert _lib.workspace_size(8, 4, 1, _lib.MGS_OP_QR64) == 768 + 512
+    with pytest.raises(_lib.MgsError):
+        _lib.workspace_size(8, 4, 2, _lib.MGS_OP_QR64)
