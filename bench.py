@@ -133,6 +133,12 @@ def precision_form(torch, api, n=2048, reps=2):
     out = {"workload": "complex %dx%d A = U diag(sigma) V^H (4+4 Householder reflectors, sigma log-spaced, "
                        "kappa 1e10), b = A x_true exactly rounded to qd" % (n, n),
            "inputs_s": t_gen}
+    # loss of orthogonality of the FP64 blocked factors (mgs_qr64)
+    f64 = api.mgs_qr64(torch.from_numpy(np.ascontiguousarray(d["A64"][0])).to(dev))
+    torch.cuda.synchronize()
+    Qh = f64["Q"].cpu().numpy()
+    Qc = (Qh[0] + 1j * Qh[1]).T
+    out["fp64_orthogonality"] = float(np.linalg.norm(Qc.conj().T @ Qc - np.eye(n), 2))
     for L, name in ((2, "dd"), (4, "qd")):
         A = np.zeros((L,) + d["A64"].shape[1:])
         A[0] = d["A64"][0]
@@ -154,10 +160,19 @@ def precision_form(torch, api, n=2048, reps=2):
         fr, tr = timed(lambda: api.refine_lstsq(At, bt, max_iter=30))
         ep = _exact_rel_err(fp["x"].cpu().numpy(), d["x_true"])
         er = _exact_rel_err(fr["x"].cpu().numpy(), d["x_true"])
+        iters = int(fr["iters"].item())
+        # error after 0, 1, ..., iters refinement steps (x_0: the FP64 solve)
+        hist = []
+        for k in range(iters + 1):
+            fk = api.refine_lstsq(At, bt, max_iter=k)
+            torch.cuda.synchronize()
+            hist.append(_exact_rel_err(fk["x"].cpu().numpy(), d["x_true"]))
         out[name] = {"plain_ms": tp, "refined_ms": tr, "plain_err": ep, "refined_err": er,
-                     "iters": int(fr["iters"].item()), "info": int(fr["info"].item()),
+                     "iters": iters, "info": int(fr["info"].item()),
                      "speedup": tp / tr, "refined_reaches_plain_error": er <= ep,
-                     "refined_within_10x_plain_error": er <= 10 * ep}
+                     "refined_within_10x_plain_error": er <= 10 * ep,
+                     "err_by_iteration": hist,
+                     "contraction": [hist[k + 1] / hist[k] for k in range(len(hist) - 1) if hist[k] > 0]}
         print("bench: precision form %s plain %.1f ms err %.2e | refined %.1f ms err %.2e iters %d" %
               (name, tp, ep, tr, er, out[name]["iters"]), file=sys.stderr, flush=True)
     return out
@@ -183,9 +198,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-form", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0)
+    ap.add_argument("--only-precision-form", action="store_true")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.only_precision_form:
+        import torch
+
+        from paper_1210_0800_amd import api
+
+        print(json.dumps({"precision_form": precision_form(torch, api)}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,

@@ -296,8 +296,8 @@ int factor64(int m, int n, const RefineWork &w, int *info, hipStream_t st) {
       const double *Qp = w.Q64 + (size_t)k0 * m;
       double *At = w.Q64 + (size_t)(k0 + nb) * m;
       double *Wb = w.R64 + (size_t)(k0 + nb) * n + k0;
-      hipLaunchKernelGGL(zgemm_qha_kernel, dim3(ceil_div(N, 16)), dim3(256), 0, st, m, N, nb, Qp, m, At, m, planeQ,
-                         Wb, n, planeR);
+      hipLaunchKernelGGL(zgemm_qha_kernel, dim3(ceil_div(N, 16)), dim3(256 * QHA_SLICES), 0, st, m, N, nb, Qp, m, At,
+                         m, planeQ, Wb, n, planeR);
       const int tiles = ceil_div(m, 16) * ceil_div(N, 16);
       hipLaunchKernelGGL(zgemm_update_kernel, dim3(ceil_div(tiles, 4)), dim3(256), 0, st, m, N, nb, Qp, m, At, m,
                          planeQ, Wb, n, planeR);

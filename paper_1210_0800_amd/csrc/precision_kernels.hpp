@@ -31,24 +31,32 @@ constexpr int NBP = 64;  // panel width of the blocked factorisation
 // W (NBP x N) = Q_p^H (NBP x m) A_t (m x N), complex, planar FP64.
 // Q_p: the panel's first column (plane stride plane), A_t: the first
 // trailing column, W: output with leading dimension ldw (R's block row).
-// One block = 4 waves = the 4 row tiles (16 panel columns each) of one
-// 16-column tile of W; K = m in steps of 4.
-__global__ __launch_bounds__(256) void zgemm_qha_kernel(int m, int N, int nbp, const double *Qp, int ldq,
-                                                         const double *At, int lda, size_t plane, double *W,
-                                                         int ldw, size_t planeW) {
+// One workgroup = 16 waves for one 16-column tile of W: wave w computes
+// the row tile w % 4 (16 panel columns) over the K slice w / 4 (a quarter
+// of the m rows, in steps of 4); the four slice partials are then summed
+// in slice order through LDS, so the result does not depend on timing.
+constexpr int QHA_SLICES = 4;
+__global__ __launch_bounds__(256 * QHA_SLICES) void zgemm_qha_kernel(int m, int N, int nbp, const double *Qp, int ldq,
+                                                                      const double *At, int lda, size_t plane,
+                                                                      double *W, int ldw, size_t planeW) {
+  __shared__ double red[QHA_SLICES - 1][4][64][8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i0 = wave * 16;          // panel column tile
+  const int tr = wave & 3, ks = wave >> 2;
+  const int i0 = tr * 16;            // panel column tile
   const int j0 = blockIdx.x * 16;    // trailing column tile
   const int li = lane & 15, lk = lane >> 4;
   const int qc = i0 + li;            // panel column read by this lane (A operand)
   const int tc = j0 + li;            // trailing column read by this lane (B operand)
   const bool qok = qc < nbp, tok = tc < N;
+  const int mq = ((m + 4 * QHA_SLICES - 1) / (4 * QHA_SLICES)) * 4;  // rows per slice, multiple of 4
+  const int k0 = ks * mq, k1 = min(m, k0 + mq);
   v4d cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
   const double *qr = Qp + (size_t)qc * ldq, *qi = qr + plane;
   const double *ar = At + (size_t)tc * lda, *ai = ar + plane;
-  for (int k = 0; k < m; k += 4) {
+#pragma unroll 4
+  for (int k = k0; k < k1; k += 4) {
     const int row = k + lk;
-    const bool rok = row < m;
+    const bool rok = row < k1;
     const double a_r = (qok && rok) ? qr[row] : 0.0, a_i = (qok && rok) ? qi[row] : 0.0;
     const double b_r = (tok && rok) ? ar[row] : 0.0, b_i = (tok && rok) ? ai[row] : 0.0;
     // conj(q) a: re = qr ar + qi ai, im = qr ai - qi ar
@@ -56,6 +64,23 @@ __global__ __launch_bounds__(256) void zgemm_qha_kernel(int m, int N, int nbp, c
     cr = mfma16x16x4(a_i, b_i, cr);
     ci = mfma16x16x4(a_r, b_i, ci);
     ci = mfma16x16x4(-a_i, b_r, ci);
+  }
+  if (ks > 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      red[ks - 1][tr][lane][r] = cr[r];
+      red[ks - 1][tr][lane][4 + r] = ci[r];
+    }
+  }
+  __syncthreads();
+  if (ks != 0) return;
+#pragma unroll
+  for (int s = 0; s < QHA_SLICES - 1; ++s) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      cr[r] += red[s][tr][lane][r];
+      ci[r] += red[s][tr][lane][4 + r];
+    }
   }
   const int oc = j0 + li;
   if (oc < N) {
