@@ -158,32 +158,48 @@ struct Resident {
   int tid, wave, lane;
   int cidx[CB];  // column of each slot, ascending; RES_NONE when empty
   C col[CB][RR];
-  Acc (*part)[NW][CB];     // LDS: [2][NW][CB] partial sums
-  int par;
+  static constexpr int NA = sizeof(Acc) / sizeof(double);  // doubles per accumulator
+  static_assert(CB <= NW, "one reducing wave per column slot");
+  double (*red)[NA][RWG];  // LDS: per-thread partial sums, [CB][NA][RWG]
+  Acc *rsum;               // LDS: reduced sums, [CB]
 
-  __device__ __forceinline__ Resident(const ResArgs &args, Acc (*p)[NW][CB]) : a(args), part(p), par(0) {
+  __device__ __forceinline__ Resident(const ResArgs &args, double (*r)[NA][RWG], Acc *rs)
+      : a(args), red(r), rsum(rs) {
     tid = threadIdx.x;
     wave = tid >> 6;
     lane = tid & 63;
   }
 
-  // Sum of the wave partials [W0, W0 + CNT) of slot s in a fixed pairwise
-  // tree (the same in every thread; few partials live at a time).
-  template <int W0, int CNT>
-  __device__ __forceinline__ Acc merge_tree(int s, bool re_only) const {
-    if constexpr (CNT == 1) {
-      return part[par][W0][s];
-    } else {
-      Acc x = merge_tree<W0, CNT / 2>(s, re_only);
-      const Acc y = merge_tree<W0 + CNT / 2, CNT / 2>(s, re_only);
-      if (re_only)
-        P::acc_merge_re(x, y);
-      else
-        P::acc_merge(x, y);
-      return x;
-    }
+  // Block reductions: every thread stores its partial sum of slot s, then
+  // (after a barrier) wave s alone reduces it: lane l merges the partials
+  // of threads l, l+64, ..., l+64(NW-1) in that order, then a DPP scan
+  // brings the total to lane 63, which writes rsum[s].  A second barrier
+  // makes rsum visible.  The merge tree is fixed, so results are
+  // reproducible, and each partial is merged once (not once per wave).
+  __device__ __forceinline__ void put(int s, const Acc &v) {
+    const double *d = reinterpret_cast<const double *>(&v);
+#pragma unroll
+    for (int c = 0; c < NA; ++c) red[s][c][tid] = d[c];
   }
-  __device__ __forceinline__ Acc merge_parts(int s, bool re_only) const { return merge_tree<0, NW>(s, re_only); }
+  __device__ __forceinline__ void reduce_slot(int s, bool re_only) {
+    Acc t;
+    double *dt = reinterpret_cast<double *>(&t);
+#pragma unroll
+    for (int c = 0; c < NA; ++c) dt[c] = red[s][c][lane];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      Acc u;
+      double *du = reinterpret_cast<double *>(&u);
+#pragma unroll
+      for (int c = 0; c < NA; ++c) du[c] = red[s][c][lane + 64 * w];
+      if (re_only)
+        P::acc_merge_re(t, u);
+      else
+        P::acc_merge(t, u);
+    }
+    wave_sum_dpp(t, re_only);
+    if (lane == 63) rsum[s] = t;
+  }
 
   // r_kj for the slots s whose column lies in (k, hi) and >= lo: the inner
   // products of q with those columns, one block reduction, the R / y
@@ -202,17 +218,20 @@ struct Resident {
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
       constexpr int s = decltype(sI)::value;
       const int j = cidx[s];
-      if (j > k && j >= lo && j < hi) {
-        wave_sum_dpp(acc[s], false);
-        if (lane == 63) part[par][wave][s] = acc[s];
-      }
+      if (j > k && j >= lo && j < hi) put(s, acc[s]);
+    });
+    lds_barrier();
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      const int j = cidx[s];
+      if (j > k && j >= lo && j < hi && wave == s) reduce_slot(s, false);
     });
     lds_barrier();
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
       constexpr int s = decltype(sI)::value;
       const int j = cidx[s];
       if (j > k && j >= lo && j < hi) {
-        const C rk = P::acc_value(merge_parts(s, false));
+        const C rk = P::acc_value(rsum[s]);
         if (tid == 0) {
           if (j < a.n)
             P::store(a.R + (size_t)j * a.ldr + k, a.planeR, rk);
@@ -223,7 +242,6 @@ struct Resident {
         for (int r = 0; r < RR; ++r) P::upd(col[s][r], rk, q[r]);
       }
     });
-    par ^= 1;
   }
 
   // r_kk = ||a_k||, q_k = a_k / r_kk for the slot holding column k; q_k
@@ -239,11 +257,11 @@ struct Resident {
         for (int r = 0; r < RR; ++r) P::acc_abs2(nacc, col[s][r]);
       }
     });
-    wave_sum_dpp(nacc, true);
-    if (lane == 63) part[par][wave][0] = nacc;
+    put(0, nacc);
     lds_barrier();
-    const Rl s2 = P::acc_value_re(merge_parts(0, true));
-    par ^= 1;
+    if (wave == 0) reduce_slot(0, true);
+    lds_barrier();
+    const Rl s2 = P::acc_value_re(rsum[0]);
     if (!P::ok_norm(s2) && tid == 0) atomicCAS(a.info, 0, k + 1);
     const Rl rkk = P::sqrt_(s2);
     const Rl inv = P::recip(rkk);
@@ -466,11 +484,11 @@ struct Resident {
       P::acc_zero(nacc);
 #pragma unroll
       for (int r = 0; r < RR; ++r) P::acc_abs2(nacc, q[r]);
-      wave_sum_dpp(nacc, true);
-      if (lane == 63) part[par][wave][0] = nacc;
+      put(0, nacc);
       lds_barrier();
-      const Acc t = merge_parts(0, true);
-      par ^= 1;
+      if (wave == 0) reduce_slot(0, true);
+      lds_barrier();
+      const Acc t = rsum[0];
       if (tid == 0) {
         const Rl s2 = P::acc_value_re(t);
         P::store_real(a.rho, 1, P::ok_norm(s2) ? P::sqrt_(s2) : P::rzero());
@@ -491,8 +509,10 @@ template <class P, int RR, int CB, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4))) void mgs_resident_kernel(
     ResArgs a) {
   using Acc = typename P::Acc;
-  __shared__ Acc part[2][NW][CB];
-  Resident<P, RR, CB, NW> st(a, part);
+  constexpr int NA = sizeof(Acc) / sizeof(double);
+  __shared__ double red[CB][NA][64 * NW];
+  __shared__ Acc rsum[CB];
+  Resident<P, RR, CB, NW> st(a, red, rsum);
   st.run();
 }
 
