@@ -159,7 +159,6 @@ struct Resident {
   int cidx[CB];  // column of each slot, ascending; RES_NONE when empty
   C col[CB][RR];
   static constexpr int NA = sizeof(Acc) / sizeof(double);  // doubles per accumulator
-  static_assert(CB <= NW, "one reducing wave per column slot");
   double (*red)[NA][RWG];  // LDS: per-thread partial sums, [CB][NA][RWG]
   Acc *rsum;               // LDS: reduced sums, [CB]
 
@@ -171,8 +170,8 @@ struct Resident {
   }
 
   // Block reductions: every thread stores its partial sum of slot s, then
-  // (after a barrier) wave s alone reduces it: lane l merges the partials
-  // of threads l, l+64, ..., l+64(NW-1) in that order, then a DPP scan
+  // (after a barrier) wave s mod NW alone reduces it: lane l merges the partials
+  // of threads l, l+64, ..., l+64(NW-1) in a pairwise tree, then a DPP scan
   // brings the total to lane 63, which writes rsum[s].  A second barrier
   // makes rsum visible.  The merge tree is fixed, so results are
   // reproducible, and each partial is merged once (not once per wave).
@@ -181,22 +180,28 @@ struct Resident {
 #pragma unroll
     for (int c = 0; c < NA; ++c) red[s][c][tid] = d[c];
   }
-  __device__ __forceinline__ void reduce_slot(int s, bool re_only) {
-    Acc t;
-    double *dt = reinterpret_cast<double *>(&t);
-#pragma unroll
-    for (int c = 0; c < NA; ++c) dt[c] = red[s][c][lane];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) {
+  // Partials of threads lane + 64 w, w in [W0, W0 + CNT), merged in a
+  // fixed pairwise tree.
+  template <int W0, int CNT>
+  __device__ __forceinline__ Acc red_tree(int s, bool re_only) const {
+    if constexpr (CNT == 1) {
       Acc u;
       double *du = reinterpret_cast<double *>(&u);
 #pragma unroll
-      for (int c = 0; c < NA; ++c) du[c] = red[s][c][lane + 64 * w];
+      for (int c = 0; c < NA; ++c) du[c] = red[s][c][lane + 64 * W0];
+      return u;
+    } else {
+      Acc x = red_tree<W0, CNT / 2>(s, re_only);
+      const Acc y = red_tree<W0 + CNT / 2, CNT / 2>(s, re_only);
       if (re_only)
-        P::acc_merge_re(t, u);
+        P::acc_merge_re(x, y);
       else
-        P::acc_merge(t, u);
+        P::acc_merge(x, y);
+      return x;
     }
+  }
+  __device__ __forceinline__ void reduce_slot(int s, bool re_only) {
+    Acc t = red_tree<0, NW>(s, re_only);
     wave_sum_dpp(t, re_only);
     if (lane == 63) rsum[s] = t;
   }
@@ -205,26 +210,22 @@ struct Resident {
   // products of q with those columns, one block reduction, the R / y
   // stores and the updates a_j -= r_kj q.
   __device__ __forceinline__ void apply(const C (&q)[RR], int k, int lo, int hi) {
-    Acc acc[CB];
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
       constexpr int s = decltype(sI)::value;
-      P::acc_zero(acc[s]);
       const int j = cidx[s];
       if (j > k && j >= lo && j < hi) {
+        Acc acc;
+        P::acc_zero(acc);
 #pragma unroll
-        for (int r = 0; r < RR; ++r) P::acc_cmulc(acc[s], q[r], col[s][r]);
+        for (int r = 0; r < RR; ++r) P::acc_cmulc(acc, q[r], col[s][r]);
+        put(s, acc);
       }
-    });
-    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
-      constexpr int s = decltype(sI)::value;
-      const int j = cidx[s];
-      if (j > k && j >= lo && j < hi) put(s, acc[s]);
     });
     lds_barrier();
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
       constexpr int s = decltype(sI)::value;
       const int j = cidx[s];
-      if (j > k && j >= lo && j < hi && wave == s) reduce_slot(s, false);
+      if (j > k && j >= lo && j < hi && wave == s % NW) reduce_slot(s, false);
     });
     lds_barrier();
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
