@@ -423,19 +423,20 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 // front.
 // Blocked form of the same back substitution: one workgroup of BS_T
 // threads, thread t holding y_j for j = s*BS_T + t.  The columns are taken
-// in blocks [k0, k0 + BS_B) from the bottom.  For each block:
+// in blocks [k0, k0 + B) from the bottom (B = 64, 32 in qd).  For each block:
 //   1. its upper triangle of R is staged in LDS;
-//   2. the one wave that holds rows k0 .. k0+BS_B-1 solves the block:
+//   2. the one wave that holds rows k0 .. k0+B-1 solves the block:
 //      x_k = y_k / r_kk (owner lane), x_k broadcast by readlane, then
 //      y_j -= r_jk x_k for the block rows j < k;
 //   3. every thread with a row j < k0 applies y_j -= r_jk x_k for the
 //      block's k in descending order (R read from global, coalesced).
 // Each y_j still receives r_jk x_k in the order k = n, n-1, ..., j+1 of
 // Figure 3 with the same operations, so x is bitwise that of the
-// column-oriented loop; the serial chain is BS_B readlane steps per block
+// column-oriented loop; the serial chain is B readlane steps per block
 // instead of one block barrier per column.
 constexpr int BS_T = 1024;
-constexpr int BS_B = 32;
+// Block width: 64 (one full wave; R block 128 KiB of LDS in dd), 32 in qd.
+constexpr int bs_block(int L) { return L == 4 ? 32 : 64; }
 
 template <class P>
 __device__ __forceinline__ typename P::C bs_readlane(const typename P::C &v, int lane) {
@@ -460,6 +461,7 @@ __global__ __launch_bounds__(BS_T) void backsolve_blocked_kernel(int n, const do
   using C = typename P::C;
   using Rl = typename P::R;
   constexpr int NP = 2 * P::L;  // planes of a complex element
+  constexpr int BS_B = bs_block(P::L);
   __shared__ double rb[NP * BS_B * BS_B];  // block of R, planar [p][col][row]
   __shared__ double xs[NP * BS_B];         // x of the block, planar [p][k]
   __shared__ int bad;
