@@ -236,7 +236,8 @@ struct RefineWork {
 };
 RefineWork refine_layout(int m, int n, int prec, void *base) {
   const int nchunk = ceil_div(n, NBP);
-  const size_t acc_bytes = prec == 2 ? 32 : 64;
+  const size_t acc_bytes = sizeof(PrecQD::Acc);  // the residual accumulates in qd
+  (void)prec;
   size_t off = 0;
   auto take = [&](size_t b) {
     size_t o = off;
@@ -324,10 +325,10 @@ int refine_solve(int m, int n, const double *A, int lda, const double *b, double
   hipLaunchKernelGGL((set_x_kernel<P>), dim3(ceil_div(n, 256)), dim3(256), 0, st, n, w.d64, x);
   const int nchunk = ceil_div(n, NBP);
   for (int it = 1; it <= max_iter; ++it) {
-    hipLaunchKernelGGL((residual_partial_kernel<P>), dim3(ceil_div(m, 256), nchunk), dim3(256), 0, st, m, n, NBP, A,
-                       lda, b, x, static_cast<typename P::Acc *>(w.partial), w.ctl);
-    hipLaunchKernelGGL((residual_finish_kernel<P>), dim3(ceil_div(m, 256)), dim3(256), 0, st, m, nchunk,
-                       static_cast<const typename P::Acc *>(w.partial), w.r64, w.ctl);
+    hipLaunchKernelGGL((residual_partial_kernel<P::L>), dim3(ceil_div(m, 256), nchunk), dim3(256), 0, st, m, n, NBP,
+                       A, lda, b, x, static_cast<PrecQD::Acc *>(w.partial), w.ctl);
+    hipLaunchKernelGGL((residual_finish_kernel<PrecQD>), dim3(ceil_div(m, 256)), dim3(256), 0, st, m, nchunk,
+                       static_cast<const PrecQD::Acc *>(w.partial), w.r64, w.ctl);
     for (int k0 = 0; k0 < n; k0 += NBP) {
       const int nb = n - k0 < NBP ? n - k0 : NBP;
       const double *Qp = w.Q64 + (size_t)k0 * m;

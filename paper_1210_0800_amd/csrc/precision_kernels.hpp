@@ -221,26 +221,43 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(double *p, size_t count)
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) p[i] = 0.0;
 }
 
-// r = b - A x in precision P, split over column chunks: block (rb, cb) sums
-// the columns [cb*CH, cb*CH + CH) of rows rb*256 .. into partial[cb][row].
-template <class P>
+// r = b - A x accumulated in quad-double whatever the working precision
+// (A, b, x stored with LP limbs are widened exactly), split over column
+// chunks: block (rb, cb) sums the columns [cb*CH, cb*CH + CH) of rows
+// rb*256 .. into partial[cb][row].  Only the FP64 rounding of r feeds the
+// correction; twice the working precision for dd keeps the residual's own
+// error below the dd solution's.
+template <int LP>
+__device__ __forceinline__ cqd load_qd_from(const double *p, size_t plane) {
+  cqd v;
+  v.re.x0 = p[0];
+  v.im.x0 = p[plane];
+  v.re.x1 = LP > 1 ? p[2 * plane] : 0.0;
+  v.im.x1 = LP > 1 ? p[3 * plane] : 0.0;
+  v.re.x2 = LP > 2 ? p[4 * plane] : 0.0;
+  v.im.x2 = LP > 2 ? p[5 * plane] : 0.0;
+  v.re.x3 = LP > 2 ? p[6 * plane] : 0.0;
+  v.im.x3 = LP > 2 ? p[7 * plane] : 0.0;
+  return v;
+}
+template <int LP>
 __global__ __launch_bounds__(256) void residual_partial_kernel(int m, int n, int chunk, const double *A, int lda,
                                                                 const double *b, const double *x,
-                                                                typename P::Acc *partial, const RefineCtl *ctl) {
+                                                                PrecQD::Acc *partial, const RefineCtl *ctl) {
   if (ctl->status != 0) return;
-  using Acc = typename P::Acc;
+  using P = PrecQD;
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int cb = blockIdx.y;
   if (i >= m) return;
   const size_t planeA = (size_t)lda * n;
-  Acc acc;
+  P::Acc acc;
   if (cb == 0)
-    P::acc_set(acc, P::load(b + i, (size_t)m));
+    P::acc_set(acc, load_qd_from<LP>(b + i, (size_t)m));
   else
     P::acc_zero(acc);
   const int j1 = min(n, (cb + 1) * chunk);
   for (int j = cb * chunk; j < j1; ++j)
-    P::acc_cmul(acc, P::load(A + (size_t)j * lda + i, planeA), P::cneg(P::load(x + j, (size_t)n)));
+    P::acc_cmul(acc, load_qd_from<LP>(A + (size_t)j * lda + i, planeA), P::cneg(load_qd_from<LP>(x + j, (size_t)n)));
   partial[(size_t)cb * m + i] = acc;
 }
 

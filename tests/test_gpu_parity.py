@@ -224,3 +224,21 @@ def test_scaling_and_real_symmetries_bitwise(prec):
     br[:, 1] = 0
     gr = gpu_lstsq(Ar, br)
     assert np.all(gr["Q"][:, 1] == 0) and np.all(gr["R"][:, 1] == 0) and np.all(gr["x"][:, 1] == 0)
+
+
+def test_resident_schedule_applies_where_documented():
+    """The single-launch schedule is taken for dd with m <= 1024 and refused
+    (MGS_ERR_DIMS when it is required) for qd and for m > 1024."""
+    from paper_1210_0800_amd import _lib
+
+    for prec, m, n, ok in ((2, 1024, 1024, True), (2, 300, 200, True), (2, 1100, 40, False), (4, 300, 200, False)):
+        p = inputs.random_problem(prec, m, n, seed=m + n, config=58)
+        with schedule("resident"):
+            if ok:
+                f = api.mgs_qr(T(p["A"]), T(p["b"]))
+                torch.cuda.synchronize()
+                assert int(f["info"].item()) == 0
+            else:
+                with pytest.raises(_lib.MgsError) as e:
+                    api.mgs_qr(T(p["A"]), T(p["b"]))
+                assert e.value.status == -1

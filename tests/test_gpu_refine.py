@@ -2,8 +2,10 @@
 
 Reference: config4 builds b as the exact product A x_true rounded to qd, so
 x_true solves the stored system to about kappa 2^-212 (1e-53 at kappa 1e10).
-Bar: the refined dd / qd solution is at least as accurate as the plain dd /
-qd MGS solution on the same GPU (within a factor 10), and converges.
+Bar: the refined dd / qd solution reaches the error of the plain dd / qd
+MGS solution on the same GPU (the residual is accumulated in qd, so the
+refined error is not limited by the working precision's residual), and
+the iteration converges.
 """
 import numpy as np
 import pytest
@@ -57,7 +59,7 @@ def test_refined_matches_plain_accuracy_n256(L):
     plain, refined, iters, info, est = solve_both(d, L)
     print("n=256 L=%d plain %.3e refined %.3e iters %d info %d est %.2e" % (L, plain, refined, iters, info, est))
     assert info == 0 and 1 <= iters <= 25
-    assert refined <= 10 * max(plain, (1e-30 if L == 2 else 1e-60))
+    assert refined <= plain
     assert plain <= (1e-19 if L == 2 else 1e-49)
 
 
@@ -66,7 +68,7 @@ def test_refined_dd_config4_2048():
     plain, refined, iters, info, est = solve_both(d, 2)
     print("n=2048 dd plain %.3e refined %.3e iters %d info %d" % (plain, refined, iters, info))
     assert info == 0 and iters <= 12
-    assert refined <= 10 * plain
+    assert refined <= plain
 
 
 def test_refinement_reports_failure_to_converge():
