@@ -10,7 +10,8 @@ Prints one JSON line: solves/s, the roofline of the dominant kernel sequence
 (the MGS factorisation, FP64 vector ALU bound), the CPU oracle baseline and
 the precision form measured against plain MGS at equal error on the
 2048 x 2048, kappa = 1e10 workload (time, error against x_true, iterations,
-in dd and qd).
+in dd and qd), and small square solves beside the paper's Tesla C2050
+figures (context only).
 
 --copy-probe BYTES only copies a device buffer of that size (for scaling the
 HBM counters of a profiler run) and exits.
@@ -178,6 +179,56 @@ def precision_form(torch, api, n=2048, reps=2):
     return out
 
 
+# The paper's Tesla C2050 figures (Table 5: 10,000 runs of MGS followed by
+# one back substitution, square random complex matrices), as solves/s.
+PAPER_C2050_SOLVES_PER_S = {("dd", 32): 10000 / 22.44, ("dd", 80): 10000 / 79.11,
+                            ("qd", 32): 10000 / 155.32, ("qd", 80): 10000 / 597.47}
+
+
+def paper_context(torch, api, solves=2000):
+    """Small square solves back to back on one stream, as the paper times
+    them, beside its C2050 numbers (other hardware: context, not a target)."""
+    from paper_1210_0800_amd import inputs
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    out = {"protocol": "%d back-to-back MGS on [A b] + back substitution, square random complex A "
+                       "(re/im of every limb level ~ U[-1,1]), one stream" % solves,
+           "paper_hardware": "NVIDIA Tesla C2050 (1147 MHz), CUDA 4.0; paper Table 5"}
+    for prec, name in ((2, "dd"), (4, "qd")):
+        for n in (32, 80):
+            p = inputs.random_problem(prec, n, n, seed=n, config=80)
+            A, b = torch.from_numpy(p["A"]).to(dev), torch.from_numpy(p["b"]).to(dev)
+            Q = torch.empty_like(A)
+            R = torch.empty((prec, 2, n, n), dtype=torch.float64, device=dev)
+            y = torch.empty((prec, 2, n), dtype=torch.float64, device=dev)
+            x = torch.empty_like(y)
+            info = torch.empty(1, dtype=torch.int32, device=dev)
+            info2 = torch.empty(1, dtype=torch.int32, device=dev)
+            work = api.workspace(n, n, prec, 0, dev)
+
+            def one():
+                api.mgs_qr(A, b, Q=Q, R=R, y=y, info=info, work=work, with_rho=False)
+                api.ls_backsolve(R, y, x=x, info=info2)
+
+            for _ in range(20):
+                one()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(solves):
+                one()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rate = solves / (e0.elapsed_time(e1) * 1e-3)
+            paper = PAPER_C2050_SOLVES_PER_S[(name, n)]
+            out["%s_n%d" % (name, n)] = {"solves_per_s": rate, "paper_c2050_solves_per_s": paper,
+                                         "ratio": rate / paper}
+            print("bench: context %s n=%d: %.0f solves/s (paper C2050 %.1f)" % (name, n, rate, paper),
+                  file=sys.stderr, flush=True)
+    return out
+
+
 def copy_probe(nbytes):
     import torch
 
@@ -306,6 +357,7 @@ def main():
     }
     if not args.no_precision_form:
         out["precision_form"] = precision_form(torch, api)
+        out["paper_context"] = paper_context(torch, api)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host[:4])
     print(json.dumps(out), flush=True)
