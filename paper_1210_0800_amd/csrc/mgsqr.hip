@@ -399,7 +399,7 @@ bool res_choose(int m, int ncols, int cus, ResPlan &pl) {
   const int rr = pow2_at_least(ceil_div(m, 64 * RES_NW));
   if (rr > 2) return false;
   const int cb = res_cb(rr);
-  const int bws[3] = {2, 1, 4};
+  const int bws[3] = {1, 2, 4};
   for (int bw : bws) {
     const int np = ceil_div(ncols, bw);
     const int G = np < cus ? np : cus;

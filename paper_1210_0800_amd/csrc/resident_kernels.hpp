@@ -7,13 +7,20 @@
 // order, then (j <= n) its norm r_jj and q_j = a_j / r_jj.  Only the
 // schedule is new:
 //
-//  * The columns are cut into panels of `bw` consecutive columns.  Panel
-//    p belongs to one workgroup; the NW waves of a workgroup split the
-//    rows (thread t holds rows r*64*NW + t, r < RR, of every column it
-//    owns), so inner products and norms are wave scans plus an NW-way
-//    exchange through LDS, and each projection costs one block barrier.
-//    Several waves per SIMD (NW = 8 or 16) hide the latency of the
-//    dependent double-double operations.
+//  * The columns are cut into panels of `bw` consecutive columns (one,
+//    by default).  Panel p belongs to one workgroup; the NW waves of a
+//    workgroup split the rows (thread t holds rows r*64*NW + t, r < RR, of
+//    every column it owns), so inner products and norms are block sums
+//    over the workgroup.  Two waves per SIMD hide part of the latency of
+//    the dependent double-double operations.
+//  * Two kinds of step.  A bulk projection (apply) sums the inner
+//    products of many columns at once: partials through LDS, one wave per
+//    column reduces, a second barrier shares the result.  A critical-path
+//    step (panel_step: the projections onto a panel about to be factored,
+//    and its normalisations) sums each wave's partial by a DPP scan and
+//    exchanges only the NW wave totals, which every thread merges: one
+//    barrier per sum, and a column's norm is accumulated while it
+//    receives its last projection.
 //  * Panels are dealt to the G workgroups in a reflected cyclic order
 //    counted from the last panel (workgroup g gets panels np-1-g,
 //    np-1-(2G-1-g), np-1-(2G+g), ...), so that every workgroup owns about
@@ -23,7 +30,8 @@
 //    same rows (r*64*NW + 64w + lane), so wave w of a consumer only needs the
 //    rows written by wave w of the producer.  The producer wave writes its
 //    rows with device-scope (write-through) stores, waits for them to
-//    complete, then stores the counter; the consumer wave polls its
+//    complete (when another step of the same panel follows, after that
+//    step's updates), then stores the counter; the consumer wave polls its
 //    counter and reads the rows with device-scope loads.  Neither side
 //    needs a workgroup barrier, an L2 write-back or an L2 invalidation.
 //    Publication is in the order k = 0, 1, ..., so one counter per wave
@@ -76,6 +84,9 @@ constexpr int RES_NONE = 1 << 30;
 // line each), the abort flag in the last word.
 constexpr int RES_SYNC_WORDS = 256;
 constexpr int RES_ABORT = RES_SYNC_WORDS - 1;
+
+// Widest panel the resident schedule factors.
+constexpr int RES_BWMAX = 4;
 
 // Device-scope (coherent across XCDs) relaxed loads and stores of one
 // double: the q vectors exchanged between workgroups.
@@ -161,9 +172,13 @@ struct Resident {
   static constexpr int NA = sizeof(Acc) / sizeof(double);  // doubles per accumulator
   double (*red)[NA][RWG];  // LDS: per-thread partial sums, [CB][NA][RWG]
   Acc *rsum;               // LDS: reduced sums, [CB]
+  double (*xch)[RES_BWMAX][NA][NW];  // LDS: wave totals of the panel steps, [2][RES_BWMAX][NA][NW]
+  int xb = 0;              // xch buffer of the next panel-step reduction
+  int pend = 0;            // 1 + column whose publication is pending, 0 if none
 
-  __device__ __forceinline__ Resident(const ResArgs &args, double (*r)[NA][RWG], Acc *rs)
-      : a(args), red(r), rsum(rs) {
+  __device__ __forceinline__ Resident(const ResArgs &args, double (*r)[NA][RWG], Acc *rs,
+                                      double (*x)[RES_BWMAX][NA][NW])
+      : a(args), red(r), rsum(rs), xch(x) {
     tid = threadIdx.x;
     wave = tid >> 6;
     lane = tid & 63;
@@ -245,30 +260,63 @@ struct Resident {
     });
   }
 
-  // r_kk = ||a_k||, q_k = a_k / r_kk for the slot holding column k; q_k
-  // and R(k, k) are written, then published.  On return q holds q_k (this
-  // thread's rows).
-  __device__ __forceinline__ void normalize(int k, C (&q)[RR]) {
-    Acc nacc;
-    P::acc_zero(nacc);
-    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
-      constexpr int s = decltype(sI)::value;
-      if (cidx[s] == k) {
+  // Block sums on the critical path (the steps that factor a panel), with a
+  // single barrier: each wave scans its own partial (DPP), lane 63 stores
+  // the wave total, and after the barrier every thread merges the NW wave
+  // totals in the same fixed pairwise tree, so all threads hold the same
+  // sum.  Two buffers alternate: a wave can only overwrite one after every
+  // wave has passed the next barrier, i.e. finished reading it.
+  __device__ __forceinline__ void xch_put(int pos, Acc t, bool re_only) {
+    wave_sum_dpp(t, re_only);
+    if (lane == 63) {
+      const double *d = reinterpret_cast<const double *>(&t);
 #pragma unroll
-        for (int r = 0; r < RR; ++r) P::acc_abs2(nacc, col[s][r]);
-      }
-    });
-    put(0, nacc);
-    lds_barrier();
-    if (wave == 0) reduce_slot(0, true);
-    lds_barrier();
-    const Rl s2 = P::acc_value_re(rsum[0]);
-    if (!P::ok_norm(s2) && tid == 0) atomicCAS(a.info, 0, k + 1);
+      for (int c = 0; c < NA; ++c) xch[xb][pos][c][wave] = d[c];
+    }
+  }
+  template <int W0, int CNT>
+  __device__ __forceinline__ Acc xch_tree(int pos, bool re_only) const {
+    if constexpr (CNT == 1) {
+      Acc u;
+      double *du = reinterpret_cast<double *>(&u);
+#pragma unroll
+      for (int c = 0; c < NA; ++c) du[c] = xch[xb][pos][c][W0];
+      return u;
+    } else {
+      Acc x = xch_tree<W0, CNT / 2>(pos, re_only);
+      const Acc y = xch_tree<W0 + CNT / 2, CNT / 2>(pos, re_only);
+      if (re_only)
+        P::acc_merge_re(x, y);
+      else
+        P::acc_merge(x, y);
+      return x;
+    }
+  }
+
+  // Publication of q_k: this wave's device-scope stores of its rows are
+  // complete before its counter moves to k + 1.
+  __device__ __forceinline__ void publish(int k) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (lane == 0) __hip_atomic_store(a.sync + 16 * wave, (unsigned int)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __device__ __forceinline__ void flush_publish() {
+    if (pend) {
+      publish(pend - 1);
+      pend = 0;
+    }
+  }
+
+  // Given s2 = ||a_x||^2 (every thread): r_xx = sqrt(s2), q_x = a_x / r_xx
+  // in the slot of column x and in q, the stores of q_x and R(x, x), and
+  // the publication of q_x now or (publish_now false) at the next panel
+  // step, so that the stores complete behind useful work.
+  __device__ __forceinline__ void finish_norm(int x, const Rl &s2, C (&q)[RR], bool publish_now) {
+    if (!P::ok_norm(s2) && tid == 0) atomicCAS(a.info, 0, x + 1);
     const Rl rkk = P::sqrt_(s2);
     const Rl inv = P::recip(rkk);
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
       constexpr int s = decltype(sI)::value;
-      if (cidx[s] == k) {
+      if (cidx[s] == x) {
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
           col[s][r] = P::scale(col[s][r], inv);
@@ -276,7 +324,7 @@ struct Resident {
         }
       }
     });
-    double *dst = a.Q + (size_t)k * a.ldq;
+    double *dst = a.Q + (size_t)x * a.ldq;
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
       const int i = r * RWG + tid;
@@ -291,12 +339,63 @@ struct Resident {
       C d;
       d.re = rkk;
       d.im = P::rzero();
-      P::store(a.R + (size_t)k * a.ldr + k, a.planeR, d);
+      P::store(a.R + (size_t)x * a.ldr + x, a.planeR, d);
     }
-    // Publish this wave's rows: its stores are complete (device-scope)
-    // before its counter moves.
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    if (lane == 0) __hip_atomic_store(a.sync + 16 * wave, (unsigned int)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (publish_now)
+      publish(x);
+    else
+      pend = x + 1;
+  }
+
+  // One step on the critical path: r_kj = q_k^H a_j and a_j -= r_kj q_k
+  // for the owned columns j > k in [lo, hi) (at most RES_BWMAX, all in one
+  // panel), with one barrier; then, if norm_col is an owned column, its
+  // norm (accumulated right after its update), a second barrier and its
+  // normalisation (finish_norm).  An empty range [lo, hi) makes it a plain
+  // normalisation.  A pending publication is completed after the updates.
+  __device__ __forceinline__ void panel_step(C (&q)[RR], int k, int lo, int hi, int norm_col, bool publish_now) {
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      const int j = cidx[s];
+      if (j > k && j >= lo && j < hi) {
+        Acc acc;
+        P::acc_zero(acc);
+#pragma unroll
+        for (int r = 0; r < RR; ++r) P::acc_cmulc(acc, q[r], col[s][r]);
+        xch_put(j - lo, acc, false);
+      }
+    });
+    lds_barrier();
+    Acc nacc;
+    P::acc_zero(nacc);
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      const int j = cidx[s];
+      if (j > k && j >= lo && j < hi) {
+        const C rk = P::acc_value(xch_tree<0, NW>(j - lo, false));
+        if (tid == 0) {
+          if (j < a.n)
+            P::store(a.R + (size_t)j * a.ldr + k, a.planeR, rk);
+          else
+            P::store(a.y + k, (size_t)a.n, rk);
+        }
+#pragma unroll
+        for (int r = 0; r < RR; ++r) P::upd(col[s][r], rk, q[r]);
+      }
+      if (j == norm_col) {
+#pragma unroll
+        for (int r = 0; r < RR; ++r) P::acc_abs2(nacc, col[s][r]);
+      }
+    });
+    xb ^= 1;
+    flush_publish();
+    if (norm_col != RES_NONE) {
+      xch_put(0, nacc, true);
+      lds_barrier();
+      const Rl s2 = P::acc_value_re(xch_tree<0, NW>(0, true));
+      xb ^= 1;
+      finish_norm(norm_col, s2, q, publish_now);
+    }
   }
 
   __device__ __forceinline__ void copy_own(int k, C (&q)[RR]) {
@@ -388,73 +487,91 @@ struct Resident {
     // the panel's own) onto the later owned columns.
     int st = 0, seen = 0, nxt = 0, k = 0;
     int ps = 0, pe = 0, pa = 0, c = 0, kd = -1, dc = 0;
-    int qk = -1;  // q currently holds q_qk (this thread's rows)
-    bool need_norm = true;
+    int qk = -1;      // q currently holds q_qk (this thread's rows)
+    int normed = -1;  // column of the current panel already normalised
     C q[RR];
+    // Each pass performs at most one bulk projection (apply) or one
+    // critical-path step (panel_step); both have a single call site so
+    // that the loop body holds one copy of each.
     while (true) {
-      int opk = 0, lo = 0, hi = RES_NONE, src = 0;  // src: 0 remote, 1 owned, 2 published earlier, 3 normalise
+      int mode = 0;  // 0 nothing, 1 apply, 2 panel_step
+      int opk = -1, lo = 0, hi = RES_NONE, ncol = RES_NONE;
+      int qsrc = 3;  // q_opk: 0 wait and load, 1 owned column, 2 load (already seen), 3 none
+      bool pubnow = true;
       if (st == 0) {
         if (k >= kend) break;
         panel(nxt, nq, g, ps, pe);
+        pa = pe < a.n ? pe : a.n;
         if (k == ps) {
           st = 1;
           c = ps;
-          pa = pe < a.n ? pe : a.n;
-          need_norm = true;
           continue;
         }
         opk = k;
+        qsrc = 0;
         if (ps < a.n && k + a.defer >= ps) {
-          lo = ps;  // critical path first: the panel only
-          hi = pe;
+          // Critical path first: the panel only; the last projection
+          // before the panel also normalises its first column.
           if (kd < 0) kd = k;
+          mode = 2;
+          lo = ps;
+          hi = pe;
+          if (k + 1 == ps) ncol = ps;
+          pubnow = ps + 1 >= pe;
         } else {
+          mode = 1;
           lo = k + 1;
         }
       } else if (st == 1) {
-        opk = c;
-        if (need_norm) {
-          src = 3;
-        } else {
-          src = 1;
+        if (normed != c) {
+          mode = 2;  // normalisation only (the first column of the matrix)
+          hi = 0;
+          ncol = c;
+          pubnow = c + 1 >= pe;
+        } else if (c + 1 < pe) {
+          mode = 2;
+          opk = c;
+          qsrc = 1;
           lo = c + 1;
           hi = pe;
+          ncol = c + 1 < pa ? c + 1 : RES_NONE;
+          pubnow = c + 2 >= pe;
         }
       } else {
-        src = dc < ps ? 2 : 1;
+        mode = 1;
         opk = dc;
+        qsrc = dc < ps ? 2 : 1;
         lo = pe;
       }
 
-      if (src == 3) {
-        normalize(opk, q);
-      } else {
-        if (src == 0) {
-          if (!res_wait(a, opk, wave, seen)) return;
-          load_q(opk, q);
-        } else if (src == 1) {
-          if (qk != opk) copy_own(opk, q);
-        } else {
-          load_q(opk, q);  // this wave has already seen it published
-        }
-        apply(q, opk, lo, hi);
+      if (qsrc == 0) {
+        if (!res_wait(a, opk, wave, seen)) return;
+        load_q(opk, q);
+      } else if (qsrc == 1) {
+        if (qk != opk) copy_own(opk, q);
+      } else if (qsrc == 2) {
+        load_q(opk, q);  // this wave has already seen it published
       }
-      qk = opk;
+      if (qsrc != 3) qk = opk;
+      if (mode == 1) {
+        apply(q, opk, lo, hi);
+      } else if (mode == 2) {
+        panel_step(q, opk, lo, hi, ncol, pubnow);
+        if (ncol != RES_NONE) {
+          normed = ncol;
+          qk = ncol;
+        }
+      }
 
       if (st == 0) {
         ++k;
         if (k == ps && ps < a.n) {
           st = 1;
           c = ps;
-          pa = pe < a.n ? pe : a.n;
-          need_norm = true;
         }
       } else if (st == 1) {
-        if (src == 3 && c + 1 < pe) {
-          need_norm = false;
-        } else {
+        if (opk >= 0 || mode == 0) {
           ++c;
-          need_norm = true;
           if (c >= pa) {
             if (last >= pe) {
               st = 2;
@@ -477,6 +594,7 @@ struct Resident {
         }
       }
     }
+    flush_publish();
 
     // rho = ||b - Q y|| after the last projection (Equation (1)).
     if (a.rho != nullptr && last == a.n) {
@@ -513,7 +631,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
   constexpr int NA = sizeof(Acc) / sizeof(double);
   __shared__ double red[CB][NA][64 * NW];
   __shared__ Acc rsum[CB];
-  Resident<P, RR, CB, NW> st(a, red, rsum);
+  __shared__ double xch[2][RES_BWMAX][NA][NW];
+  Resident<P, RR, CB, NW> st(a, red, rsum, xch);
   st.run();
 }
 
