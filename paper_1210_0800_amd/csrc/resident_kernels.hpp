@@ -81,9 +81,16 @@ struct ResArgs {
 constexpr int RES_NONE = 1 << 30;
 
 // Synchronisation words: wave w's counter at 16 w (w < 16, one 64-byte
-// line each), the abort flag in the last word.
+// line each), the arrival count of the start barrier and the abort flag in
+// the last two words.
 constexpr int RES_SYNC_WORDS = 256;
+constexpr int RES_GRID = RES_SYNC_WORDS - 2;
 constexpr int RES_ABORT = RES_SYNC_WORDS - 1;
+
+// Bit pattern written over every q entry of Q before the factorisation: a
+// signalling NaN, which no arithmetic produces, so a reader knows an entry
+// of q_k has arrived when it differs from it.
+constexpr long long RES_EMPTY = 0x7ff4a5a5a5a5a5a5LL;
 
 // Widest panel the resident schedule factors.
 constexpr int RES_BWMAX = 4;
@@ -95,6 +102,21 @@ __device__ __forceinline__ void coh_store(double *p, double v) {
 }
 __device__ __forceinline__ double coh_load(const double *p) {
   return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Common end of a bounded wait: true (and the abort flag set, info
+// written) once the wall-clock limit has passed, or when another wave has
+// aborted.
+__device__ __forceinline__ bool res_give_up(const ResArgs &a, long long t0) {
+  if (__builtin_amdgcn_readfirstlane(
+          (int)__hip_atomic_load(a.sync + RES_ABORT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)
+    return true;
+  if (wall_clock64() - t0 > a.spin_ticks) {
+    __hip_atomic_store(a.sync + RES_ABORT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(a.info, MGS_INFO_SYNC_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+  }
+  return false;
 }
 
 // Waits until wave `wave` of the owners has published at least k+1
@@ -112,14 +134,7 @@ __device__ __forceinline__ bool res_wait(const ResArgs &a, int k, int wave, int 
       asm volatile("" ::: "memory");
       return true;
     }
-    if (__builtin_amdgcn_readfirstlane(
-            (int)__hip_atomic_load(a.sync + RES_ABORT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)
-      return false;
-    if (wall_clock64() - t0 > a.spin_ticks) {
-      __hip_atomic_store(a.sync + RES_ABORT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(a.info, MGS_INFO_SYNC_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
-    }
+    if (res_give_up(a, t0)) return false;
     __builtin_amdgcn_s_sleep(1);
   }
 }
@@ -295,9 +310,13 @@ struct Resident {
 
   // Publication of q_k: this wave's device-scope stores of its rows are
   // complete before its counter moves to k + 1.
+  // The counter only grows (atomic max): the owner of q_{k+1} can finish
+  // before this store of the owner of q_k lands, since it reads q_k itself
+  // rather than the counter.
   __device__ __forceinline__ void publish(int k) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    if (lane == 0) __hip_atomic_store(a.sync + 16 * wave, (unsigned int)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0)
+      __hip_atomic_fetch_max(a.sync + 16 * wave, (unsigned int)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __device__ __forceinline__ void flush_publish() {
     if (pend) {
@@ -407,19 +426,74 @@ struct Resident {
       }
     });
   }
-  __device__ __forceinline__ void load_q(int k, C (&q)[RR]) {
+  // Reads this thread's rows of q_k from Q, again until none of this
+  // wave's entries is still RES_EMPTY (so it also serves as the wait of the
+  // critical-path steps, which poll the data instead of the counter).
+  // Returns false on abort or time-out.
+  __device__ __forceinline__ bool load_q(int k, C (&q)[RR]) {
     const double *src = a.Q + (size_t)k * a.ldq;
+    long long t0 = -1;
+    while (true) {
+      bool miss = false;
 #pragma unroll
-    for (int r = 0; r < RR; ++r) {
-      const int i = r * RWG + tid;
-      q[r] = P::czero();
-      if (i < a.m) {
-        q[r].re.h = coh_load(src + i);
-        q[r].im.h = coh_load(src + i + a.planeQ);
-        q[r].re.l = coh_load(src + i + 2 * a.planeQ);
-        q[r].im.l = coh_load(src + i + 3 * a.planeQ);
+      for (int r = 0; r < RR; ++r) {
+        const int i = r * RWG + tid;
+        q[r] = P::czero();
+        if (i < a.m) {
+          q[r].re.h = coh_load(src + i);
+          q[r].im.h = coh_load(src + i + a.planeQ);
+          q[r].re.l = coh_load(src + i + 2 * a.planeQ);
+          q[r].im.l = coh_load(src + i + 3 * a.planeQ);
+          miss = miss || __double_as_longlong(q[r].re.h) == RES_EMPTY ||
+                 __double_as_longlong(q[r].im.h) == RES_EMPTY || __double_as_longlong(q[r].re.l) == RES_EMPTY ||
+                 __double_as_longlong(q[r].im.l) == RES_EMPTY;
+        }
+      }
+      if (__ballot(miss) == 0) return true;
+      if (t0 < 0) t0 = wall_clock64();
+      if (res_give_up(a, t0)) return false;
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  // Start of the factorisation: RES_EMPTY over the owned columns of Q
+  // (after they have been read: Q may be A), then a grid barrier, so that
+  // no entry of Q is read before it is either empty or final.
+  __device__ __forceinline__ bool mark_empty() {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the columns are in registers
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      const int j = cidx[s];
+      if (j < a.n) {
+        double *dst = a.Q + (size_t)j * a.ldq;
+        const double e = __longlong_as_double(RES_EMPTY);
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+          const int i = r * RWG + tid;
+          if (i < a.m) {
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) coh_store(dst + i + pl * a.planeQ, e);
+          }
+        }
+      }
+    });
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    bool ok = true;
+    if (tid == 0) {
+      __hip_atomic_fetch_add(a.sync + RES_GRID, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const long long t0 = wall_clock64();
+      while (__hip_atomic_load(a.sync + RES_GRID, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned int)a.G) {
+        if (res_give_up(a, t0)) {
+          ok = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
       }
     }
+    __shared__ int grid_ok;
+    if (tid == 0) grid_ok = ok ? 1 : 0;
+    __syncthreads();
+    return grid_ok != 0;
   }
   // Panel `i` of the owned list in ascending column order: [ps, pe).
   __device__ __forceinline__ void panel(int i, int nq, int g, int &ps, int &pe) const {
@@ -479,6 +553,7 @@ struct Resident {
       constexpr int s = decltype(sI)::value;
       if (cidx[s] != RES_NONE && cidx[s] > last) last = cidx[s];
     });
+    if (!mark_empty()) return;
     if (last < 0) return;
     const int kend = last < a.n ? last + 1 : a.n;
 
@@ -545,12 +620,14 @@ struct Resident {
       }
 
       if (qsrc == 0) {
-        if (!res_wait(a, opk, wave, seen)) return;
-        load_q(opk, q);
+        // Bulk projections wait on the counter; critical-path steps poll
+        // q itself, which arrives before its owner's counter moves.
+        if (mode == 1 && !res_wait(a, opk, wave, seen)) return;
+        if (!load_q(opk, q)) return;
       } else if (qsrc == 1) {
         if (qk != opk) copy_own(opk, q);
       } else if (qsrc == 2) {
-        load_q(opk, q);  // this wave has already seen it published
+        if (!load_q(opk, q)) return;  // already seen: returns at once
       }
       if (qsrc != 3) qk = opk;
       if (mode == 1) {
