@@ -250,9 +250,17 @@ def main():
     ap.add_argument("--no-precision-form", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--only-precision-form", action="store_true")
+    ap.add_argument("--only-context", action="store_true")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.only_context:
+        import torch
+
+        from paper_1210_0800_amd import api
+
+        print(json.dumps({"paper_context": paper_context(torch, api)}), flush=True)
         return
     if args.only_precision_form:
         import torch

@@ -94,6 +94,22 @@ __device__ __forceinline__ dd dd_sqrt(dd s) {
   return {hs, hl};
 }
 
+// sqrt(s) and 1/sqrt(s) together from one FP64 square root and one FP64
+// division: the root as in dd_sqrt (0.5/x is exactly half of 1/x), the
+// inverse by one Newton step on the dd root started from 1/x, so the two
+// results share their slow operations instead of chaining them.
+__device__ __forceinline__ void dd_sqrt_recip(dd s, dd &root, dd &inv) {
+  const double x = sqrt(s.h);
+  const double y = 1.0 / x;
+  double p, e;
+  two_prod(x, x, p, e);
+  const double d = ((s.h - p) - e) + s.l;
+  fast_two_sum(x, d * (0.5 * y), root.h, root.l);
+  double r = __fma_rn(-root.h, y, 1.0);
+  r = __fma_rn(-root.l, y, r);
+  fast_two_sum(y, y * r, inv.h, inv.l);
+}
+
 // ------------------------------------------------------------------- qd --
 struct qd {
   double x0, x1, x2, x3;
@@ -381,6 +397,7 @@ struct PrecDD {
   }
   __device__ static __forceinline__ R sqrt_(const R &s) { return dd_sqrt(s); }
   __device__ static __forceinline__ R recip(const R &s) { return dd_recip(s); }
+  __device__ static __forceinline__ void sqrt_recip(const R &s, R &root, R &inv) { dd_sqrt_recip(s, root, inv); }
   __device__ static __forceinline__ bool ok_norm(const R &s) {
     return s.h > 0.0 && s.h < INFINITY && s.l == s.l && fabs(s.l) < INFINITY;
   }

@@ -387,17 +387,24 @@ int res_max_cols(int ncols, int bw, int G) {
   return best;
 }
 
-// Resident shapes (dd): workgroups of RES_NW waves (2 per SIMD), RR rows
-// per thread, CB column slots per workgroup (register budget 256 per lane).
+// Resident shapes (dd): workgroups of nw waves (up to 8, 2 per SIMD), RR
+// rows per thread, CB column slots per workgroup (register budget 256 per
+// lane).  Short columns take fewer waves (64 nw >= m), so that their block
+// sums have fewer levels and their barriers fewer waves.
 constexpr int RES_NW = 8;
 constexpr int res_cb(int rr) { return rr == 1 ? 8 : 5; }
 
 struct ResPlan {
-  int rr, bw, np, G;
+  int rr, nw, bw, np, G;
 };
 bool res_choose(int m, int ncols, int cus, ResPlan &pl) {
   const int rr = pow2_at_least(ceil_div(m, 64 * RES_NW));
   if (rr > 2) return false;
+  int nw = RES_NW;
+  if (rr == 1) {
+    nw = pow2_at_least(ceil_div(m, 64));
+    if (nw > RES_NW) nw = RES_NW;
+  }
   const int cb = res_cb(rr);
   const int bws[3] = {1, 2, 4};
   for (int bw : bws) {
@@ -405,6 +412,7 @@ bool res_choose(int m, int ncols, int cus, ResPlan &pl) {
     const int G = np < cus ? np : cus;
     if (res_max_cols(ncols, bw, G) <= cb) {
       pl.rr = rr;
+      pl.nw = nw;
       pl.bw = bw;
       pl.np = np;
       pl.G = G;
@@ -416,24 +424,24 @@ bool res_choose(int m, int ncols, int cus, ResPlan &pl) {
 
 // Returns 1 when the single launch does not apply here (the caller then
 // takes the per-panel schedule).
-template <class P, int RR>
+template <class P, int RR, int NW>
 int res_launch_rr(ResArgs a, int cus, hipStream_t st) {
   constexpr int CB = res_cb(RR);
-  auto kern = mgs_resident_kernel<P, RR, CB, RES_NW>;
+  auto kern = mgs_resident_kernel<P, RR, CB, NW>;
   // Only kernels that keep everything in registers and LDS take this
   // schedule: no private (scratch) memory in a cooperative launch.
   hipFuncAttributes fa;
   if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kern)) != hipSuccess || fa.localSizeBytes != 0)
     return 1;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), 64 * RES_NW, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), 64 * NW, 0) !=
       hipSuccess)
     return 1;
   if ((long long)per_cu * cus < a.G) return 1;
   hipLaunchKernelGGL(resident_init_kernel, dim3(1), dim3(RES_SYNC_WORDS), 0, st, a.sync, a.info, 1);
   if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
   void *args[] = {&a};
-  if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(a.G), dim3(64 * RES_NW), args, 0, st) !=
+  if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(a.G), dim3(64 * NW), args, 0, st) !=
       hipSuccess) {
     (void)hipGetLastError();
     return 1;
@@ -472,9 +480,12 @@ int res_launch_dd(const StepArgs &s, void *sync, hipStream_t st) {
   a.xcd_group = pl.G % 8 == 0 ? pl.G / 8 : 0;
   a.defer = 2;
   a.spin_ticks = d.wclk_khz * 2000;  // 2 s
-  switch (pl.rr) {
-    case 1: return res_launch_rr<P, 1>(a, d.cus, st);
-    case 2: return res_launch_rr<P, 2>(a, d.cus, st);
+  if (pl.rr == 2) return res_launch_rr<P, 2, 8>(a, d.cus, st);
+  switch (pl.nw) {
+    case 1: return res_launch_rr<P, 1, 1>(a, d.cus, st);
+    case 2: return res_launch_rr<P, 1, 2>(a, d.cus, st);
+    case 4: return res_launch_rr<P, 1, 4>(a, d.cus, st);
+    case 8: return res_launch_rr<P, 1, 8>(a, d.cus, st);
   }
   return 1;
 }

@@ -331,8 +331,8 @@ struct Resident {
   // step, so that the stores complete behind useful work.
   __device__ __forceinline__ void finish_norm(int x, const Rl &s2, C (&q)[RR], bool publish_now) {
     if (!P::ok_norm(s2) && tid == 0) atomicCAS(a.info, 0, x + 1);
-    const Rl rkk = P::sqrt_(s2);
-    const Rl inv = P::recip(rkk);
+    Rl rkk, inv;
+    P::sqrt_recip(s2, rkk, inv);
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
       constexpr int s = decltype(sI)::value;
       if (cidx[s] == x) {
@@ -702,7 +702,7 @@ struct Resident {
 };
 
 template <class P, int RR, int CB, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4))) void mgs_resident_kernel(
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW < 4 ? 1 : NW / 4, NW < 4 ? 1 : NW / 4))) void mgs_resident_kernel(
     ResArgs a) {
   using Acc = typename P::Acc;
   constexpr int NA = sizeof(Acc) / sizeof(double);
