@@ -95,8 +95,10 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
  *             of the projected right-hand side, ||b - A x|| of the
  *             least-squares solution x (Equation (1)).
  *   work      workspace of mgs_workspace_size(m, n, prec, MGS_OP_QR) bytes
- *             (always required: it holds the publication counter of the
- *             single-launch factorisation and the working copy of b).
+ *             (always required: it holds the working copy of b, the
+ *             publication counters of the single-launch factorisation and,
+ *             in dd with m <= 1024, its hand-off copy of the columns,
+ *             32 m n bytes).
  *   info      device int, see above.
  * Requires 1 <= n <= m <= MGS_MAX_ROWS_{DD,QD}.
  * Schedule: in dd, when every column fits in the register file of the
@@ -104,8 +106,11 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
  * e.g. 1024 x 1024 with b on 256 compute units) the factorisation is one
  * cooperative launch with the columns held in registers; otherwise (and in
  * qd) one launch per panel of columns.
- * Both schedules perform the operations of Figure 1 in the same order per
- * column; reduction trees differ, so results agree to rounding.
+ * Both schedules apply the projections of Figure 1 in the same order per
+ * column; reduction trees differ, and in the single launch the last two
+ * projections onto each column use r_kj = (a_k^H a_j) / r_kk with a_k
+ * before its normalisation (equal to q_k^H a_j in exact arithmetic), so
+ * results agree to rounding.
  */
 int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq, double *R, int ldr,
            const double *b, double *y, double *rho, void *work, size_t work_bytes, int *info,

@@ -178,9 +178,15 @@ int project_launch(int m, int n, const double *Q, int ldq, const double *b, doub
 }
 
 // QR: working copy of b (2Lm doubles), then the synchronisation words of
-// the single-launch schedule.
+// the single-launch schedule, then (dd, m <= 1024: the shapes that can take
+// it) its hand-off copy of the n columns (2Lmn doubles).
 size_t qr_w_bytes(int m, int prec) { return round256(sizeof(double) * 2 * (size_t)prec * m); }
-size_t qr_work_bytes(int m, int prec) { return qr_w_bytes(m, prec) + sizeof(unsigned int) * RES_SYNC_WORDS; }
+size_t qr_u_bytes(int m, int n, int prec) {
+  return (prec == 2 && m <= 1024) ? round256(sizeof(double) * 2 * (size_t)prec * m * n) : 0;
+}
+size_t qr_work_bytes(int m, int n, int prec) {
+  return qr_w_bytes(m, prec) + sizeof(unsigned int) * RES_SYNC_WORDS + qr_u_bytes(m, n, prec);
+}
 size_t solve_work_bytes(int n, int prec) { return round256(sizeof(double) * 2 * (size_t)prec * n); }
 // adjoint: w (n), z (n), r (m)
 size_t adjoint_work_bytes(int m, int n, int prec) {
@@ -406,7 +412,8 @@ bool res_choose(int m, int ncols, int cus, ResPlan &pl) {
     if (nw > RES_NW) nw = RES_NW;
   }
   const int cb = res_cb(rr);
-  const int bws[3] = {1, 2, 4};
+  // Panels of one column: the look-ahead hand-off of the kernel assumes it.
+  const int bws[1] = {1};
   for (int bw : bws) {
     const int np = ceil_div(ncols, bw);
     const int G = np < cus ? np : cus;
@@ -450,7 +457,7 @@ int res_launch_rr(ResArgs a, int cus, hipStream_t st) {
 }
 
 // dd only: the qd instantiations do not fit in registers.
-int res_launch_dd(const StepArgs &s, void *sync, hipStream_t st) {
+int res_launch_dd(const StepArgs &s, void *sync, double *u, hipStream_t st) {
   using P = PrecDD;
   DevInfo d;
   if (!dev_info(d)) return 1;
@@ -474,11 +481,14 @@ int res_launch_dd(const StepArgs &s, void *sync, hipStream_t st) {
   a.rho = s.rho;
   a.info = s.info;
   a.sync = static_cast<unsigned int *>(sync);
+  a.U = u;
+  a.ldu = s.m;
+  a.planeU = (size_t)s.m * s.n;
   a.bw = pl.bw;
   a.np = pl.np;
   a.G = pl.G;
   a.xcd_group = pl.G % 8 == 0 ? pl.G / 8 : 0;
-  a.defer = 2;
+  a.defer = 16;
   a.spin_ticks = d.wclk_khz * 2000;  // 2 s
   if (pl.rr == 2) return res_launch_rr<P, 2, 8>(a, d.cus, st);
   switch (pl.nw) {
@@ -525,7 +535,7 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes) {
   if (n < 1 || m < n || m > (op == MGS_OP_QR64 ? MGS_MAX_ROWS_DD : max_rows(prec))) return MGS_ERR_DIMS;
   if (!bytes) return MGS_ERR_POINTER;
   switch (op) {
-    case MGS_OP_QR: *bytes = qr_work_bytes(m, prec); return MGS_OK;
+    case MGS_OP_QR: *bytes = qr_work_bytes(m, n, prec); return MGS_OK;
     case MGS_OP_SOLVE: *bytes = solve_work_bytes(n, prec); return MGS_OK;
     case MGS_OP_ADJOINT: *bytes = adjoint_work_bytes(m, n, prec); return MGS_OK;
     case MGS_OP_REFINE: *bytes = refine_layout(m, n, prec, nullptr).bytes; return MGS_OK;
@@ -544,7 +554,7 @@ int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq,
   if (rho && !aligned8(rho)) return MGS_ERR_POINTER;
   if (!aligned8(work)) return MGS_ERR_POINTER;
   if (b && (!aligned8(b) || !aligned8(y))) return MGS_ERR_POINTER;
-  if (work_bytes < qr_work_bytes(m, prec)) return MGS_ERR_WORKSPACE;
+  if (work_bytes < qr_work_bytes(m, n, prec)) return MGS_ERR_WORKSPACE;
   Shape sh = choose_shape(m, prec);
   StepArgs a;
   a.m = m;
@@ -571,7 +581,8 @@ int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq,
   const int mode = schedule_mode();
   if (mode != 1) {
     void *sync = static_cast<char *>(work) + qr_w_bytes(m, prec);
-    const int rc = prec == 2 ? res_launch_dd(a, sync, st) : 1;
+    double *u = reinterpret_cast<double *>(static_cast<char *>(sync) + sizeof(unsigned int) * RES_SYNC_WORDS);
+    const int rc = prec == 2 && qr_u_bytes(m, n, prec) > 0 ? res_launch_dd(a, sync, u, st) : 1;
     if (rc != 1) return rc;
     if (mode == 2) return MGS_ERR_DIMS;
   }

@@ -5,50 +5,39 @@
 // Operations are those of Figure 1 (Section 3) on the augmented matrix of
 // Equation (1): column j receives the projections k = 1, 2, ..., j-1 in
 // order, then (j <= n) its norm r_jj and q_j = a_j / r_jj.  Only the
-// schedule is new:
+// schedule, the reduction trees and one reassociation (below) are new:
 //
-//  * The columns are cut into panels of `bw` consecutive columns (one,
-//    by default).  Panel p belongs to one workgroup; the NW waves of a
-//    workgroup split the rows (thread t holds rows r*64*NW + t, r < RR, of
-//    every column it owns), so inner products and norms are block sums
-//    over the workgroup.  Two waves per SIMD hide part of the latency of
-//    the dependent double-double operations.
-//  * Two kinds of step.  A bulk projection (apply) sums the inner
-//    products of many columns at once: partials through LDS, one wave per
-//    column reduces, a second barrier shares the result.  A critical-path
-//    step (panel_step: the projections onto a panel about to be factored,
-//    and its normalisations) sums each wave's partial by a DPP scan and
-//    exchanges only the NW wave totals, which every thread merges: one
-//    barrier per sum, and a column's norm is accumulated while it
-//    receives its last projection.
-//  * Panels are dealt to the G workgroups in a reflected cyclic order
-//    counted from the last panel (workgroup g gets panels np-1-g,
-//    np-1-(2G-1-g), np-1-(2G+g), ...), so that every workgroup owns about
-//    the same triangular amount of work (a late and an early panel).
-//  * q_k is published by its owner through the output Q and one counter
-//    of published columns per wave: wave w of every workgroup holds the
-//    same rows (r*64*NW + 64w + lane), so wave w of a consumer only needs the
-//    rows written by wave w of the producer.  The producer wave writes its
-//    rows with device-scope (write-through) stores, waits for them to
-//    complete (when another step of the same panel follows, after that
-//    step's updates), then stores the counter; the consumer wave polls its
-//    counter and reads the rows with device-scope loads.  Neither side
-//    needs a workgroup barrier, an L2 write-back or an L2 invalidation.
-//    Publication is in the order k = 0, 1, ..., so one counter per wave
-//    covers every column.
-//  * Critical path first: once the factorisation front is within `defer`
-//    columns of a workgroup's next panel, the arriving q vectors are
-//    applied to that panel only; the panel is factored and published, and
-//    only then do the workgroup's later columns receive the deferred
-//    projections (re-read from Q) and the panel's own, in the order k,
-//    k+1, ...
-//  * Consecutive panels sit on the same XCD (workgroup numbering is
-//    rotated so that logical workgroups 0..G/8-1 land on one XCD), so most
-//    hand-offs stay inside one L2.
+//  * Every column is its own panel (bw = 1), owned by one workgroup; the
+//    NW waves of a workgroup split the rows (thread t holds rows r*64*NW
+//    + t, r < RR, of every column it owns), so inner products and norms
+//    are block sums over the workgroup.  Columns are dealt to the G
+//    workgroups in a reflected cyclic order counted from the last column
+//    (workgroup g gets np-1-g, np-1-(2G-1-g), np-1-(2G+g), ...), so that
+//    every workgroup owns about the same triangular amount of work.
+//  * Bulk projections (apply) sum the inner products of all of a
+//    workgroup's columns at once: partials through LDS, one wave per
+//    column reduces, a second barrier shares the result.  They read q_k
+//    from Q once its owner's counter says it is published (device-scope
+//    stores, completed before the counter moves; one counter per wave,
+//    since wave w of every workgroup holds the same rows).
+//  * The critical path (the chain column k -> column k+1) goes another
+//    way.  As soon as column k has received its last projection, its
+//    owner copies it, not yet normalised, to U and only then normalises
+//    it.  The owners of the next `defer` columns poll U[k] directly (Q and
+//    U hold a signalling-NaN pattern until written) and, in one block sum
+//    with one barrier (DPP scans per wave, the NW wave totals merged by
+//    every thread), get both ||a_k||^2 and a_k^H a_j; from these they form
+//    r_kk and q_k exactly as the owner does (same partials, same merge
+//    tree, same operations) and r_kj = (a_k^H a_j) / r_kk, equal to
+//    q_k^H a_j in exact arithmetic.  Their other columns receive these
+//    projections later, from Q, in order.
+//  * Consecutive columns sit on the same XCD (workgroup numbering is
+//    rotated so that logical workgroups 0..G/8-1 land on one XCD).
 //
-// The launch is cooperative (every workgroup resident), and every wait is
-// bounded by a wall-clock limit after which the kernel aborts through a
-// flag that all waits observe, so no wave can spin forever.
+// The launch is cooperative (every workgroup resident); it starts with a
+// grid barrier after Q and U are marked empty, and every wait is bounded by
+// a wall-clock limit after which the kernel aborts through a flag that all
+// waits observe, so no wave can spin forever.
 #pragma once
 #include "../../include/mgsqr.h"
 #include "mgs_kernels.hpp"
@@ -70,10 +59,13 @@ struct ResArgs {
   double *y;
   double *rho;
   int *info;
+  double *U;  // workspace: each column after its last projection, before normalisation (n columns)
+  int ldu;
+  size_t planeU;
   unsigned int *sync;  // RES_SYNC_WORDS words, zero at launch: per-wave counters and the abort flag
-  int bw, np, G;
+  int bw, np, G;  // bw must be 1: every panel is one column
   int xcd_group;        // logical workgroups per XCD (G / 8), 0 for identity numbering
-  int defer;            // look-ahead window of the critical-path-first rule (columns)
+  int defer;            // look-ahead window of the critical-path-first rule (columns, >= 1)
   long long spin_ticks;  // wall-clock limit of one wait
 };
 
@@ -102,6 +94,14 @@ __device__ __forceinline__ void coh_store(double *p, double v) {
 }
 __device__ __forceinline__ double coh_load(const double *p) {
   return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// The row index of a Q / U access, opaque to the compiler: keeps it from
+// hoisting the 64-bit addresses of every plane and row out of the main
+// loop, which would hold dozens of registers for the whole kernel.
+__device__ __forceinline__ int row_of(int r, int rwg) {
+  int i = r * rwg + (int)threadIdx.x;
+  asm volatile("" : "+v"(i));
+  return i;
 }
 
 // Common end of a bounded wait: true (and the abort flag set, info
@@ -189,7 +189,6 @@ struct Resident {
   Acc *rsum;               // LDS: reduced sums, [CB]
   double (*xch)[RES_BWMAX][NA][NW];  // LDS: wave totals of the panel steps, [2][RES_BWMAX][NA][NW]
   int xb = 0;              // xch buffer of the next panel-step reduction
-  int pend = 0;            // 1 + column whose publication is pending, 0 if none
 
   __device__ __forceinline__ Resident(const ResArgs &args, double (*r)[NA][RWG], Acc *rs,
                                       double (*x)[RES_BWMAX][NA][NW])
@@ -309,27 +308,54 @@ struct Resident {
   }
 
   // Publication of q_k: this wave's device-scope stores of its rows are
-  // complete before its counter moves to k + 1.
-  // The counter only grows (atomic max): the owner of q_{k+1} can finish
-  // before this store of the owner of q_k lands, since it reads q_k itself
-  // rather than the counter.
+  // complete before its counter moves to k + 1.  The counter only grows
+  // (atomic max): the owners of later columns do not wait for it (they
+  // read the unnormalised columns from U), so their stores can land first.
   __device__ __forceinline__ void publish(int k) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     if (lane == 0)
       __hip_atomic_fetch_max(a.sync + 16 * wave, (unsigned int)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  __device__ __forceinline__ void flush_publish() {
-    if (pend) {
-      publish(pend - 1);
-      pend = 0;
-    }
+
+  // This thread's rows of the owned column x, with device-scope stores,
+  // into U (the hand-off to the next two columns' owners).
+  __device__ __forceinline__ void store_u(int x) {
+    double *dst = a.U + (size_t)x * a.ldu;
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      if (cidx[s] == x) {
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+          const int i = row_of(r, RWG);
+          if (i < a.m) {
+            coh_store(dst + i, col[s][r].re.h);
+            coh_store(dst + i + a.planeU, col[s][r].im.h);
+            coh_store(dst + i + 2 * a.planeU, col[s][r].re.l);
+            coh_store(dst + i + 3 * a.planeU, col[s][r].im.l);
+          }
+        }
+      }
+    });
   }
 
-  // Given s2 = ||a_x||^2 (every thread): r_xx = sqrt(s2), q_x = a_x / r_xx
-  // in the slot of column x and in q, the stores of q_x and R(x, x), and
-  // the publication of q_x now or (publish_now false) at the next panel
-  // step, so that the stores complete behind useful work.
-  __device__ __forceinline__ void finish_norm(int x, const Rl &s2, C (&q)[RR], bool publish_now) {
+  // Normalisation of the owned column x, which has received all its
+  // projections: s2 = ||a_x||^2 (one barrier), r_xx and 1/r_xx, q_x = a_x /
+  // r_xx in the slot and in q, the stores of q_x and R(x, x), and the
+  // publication of q_x.
+  __device__ __forceinline__ void own_norm(int x, C (&q)[RR]) {
+    Acc nacc;
+    P::acc_zero(nacc);
+    static_for<CB>([&](auto sI) __attribute__((always_inline)) {
+      constexpr int s = decltype(sI)::value;
+      if (cidx[s] == x) {
+#pragma unroll
+        for (int r = 0; r < RR; ++r) P::acc_abs2(nacc, col[s][r]);
+      }
+    });
+    xch_put(0, nacc, true);
+    lds_barrier();
+    const Rl s2 = P::acc_value_re(xch_tree<0, NW>(0, true));
+    xb ^= 1;
     if (!P::ok_norm(s2) && tid == 0) atomicCAS(a.info, 0, x + 1);
     Rl rkk, inv;
     P::sqrt_recip(s2, rkk, inv);
@@ -346,7 +372,7 @@ struct Resident {
     double *dst = a.Q + (size_t)x * a.ldq;
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
-      const int i = r * RWG + tid;
+      const int i = row_of(r, RWG);
       if (i < a.m) {
         coh_store(dst + i, q[r].re.h);
         coh_store(dst + i + a.planeQ, q[r].im.h);
@@ -360,61 +386,54 @@ struct Resident {
       d.im = P::rzero();
       P::store(a.R + (size_t)x * a.ldr + x, a.planeR, d);
     }
-    if (publish_now)
-      publish(x);
-    else
-      pend = x + 1;
+    publish(x);
   }
 
-  // One step on the critical path: r_kj = q_k^H a_j and a_j -= r_kj q_k
-  // for the owned columns j > k in [lo, hi) (at most RES_BWMAX, all in one
-  // panel), with one barrier; then, if norm_col is an owned column, its
-  // norm (accumulated right after its update), a second barrier and its
-  // normalisation (finish_norm).  An empty range [lo, hi) makes it a plain
-  // normalisation.  A pending publication is completed after the updates.
-  __device__ __forceinline__ void panel_step(C (&q)[RR], int k, int lo, int hi, int norm_col, bool publish_now) {
+  // Critical-path projection of column k onto the owned column ps (k >=
+  // ps - defer), from u = a_k after its last projection, read from U (in
+  // u's registers, which hold q_k on return).  One block sum gives both
+  // ||u||^2 and u^H a_ps; then r_kk and 1/r_kk exactly as the owner of
+  // column k computes them (same partials, same merge tree, same
+  // operations), q_k = u / r_kk, r_{k,ps} = (u^H a_ps) / r_kk (equal to
+  // q_k^H a_ps up to rounding) and a_ps -= r_{k,ps} q_k.  After the last
+  // projection (k = ps - 1) column ps is final and is handed on through U
+  // before anything else.
+  __device__ __forceinline__ void lookahead_step(C (&u)[RR], int k, int ps, bool last) {
+    {
+      Acc an;
+      P::acc_zero(an);
+#pragma unroll
+      for (int r = 0; r < RR; ++r) P::acc_abs2(an, u[r]);
+      xch_put(1, an, true);
+    }
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
       constexpr int s = decltype(sI)::value;
-      const int j = cidx[s];
-      if (j > k && j >= lo && j < hi) {
-        Acc acc;
-        P::acc_zero(acc);
+      if (cidx[s] == ps) {
+        Acc ad;
+        P::acc_zero(ad);
 #pragma unroll
-        for (int r = 0; r < RR; ++r) P::acc_cmulc(acc, q[r], col[s][r]);
-        xch_put(j - lo, acc, false);
+        for (int r = 0; r < RR; ++r) P::acc_cmulc(ad, u[r], col[s][r]);
+        xch_put(0, ad, false);
       }
     });
     lds_barrier();
-    Acc nacc;
-    P::acc_zero(nacc);
+    const Rl s2 = P::acc_value_re(xch_tree<0, NW>(1, true));
+    const C d = P::acc_value(xch_tree<0, NW>(0, false));
+    xb ^= 1;
+    Rl rkk, inv;
+    P::sqrt_recip(s2, rkk, inv);
+#pragma unroll
+    for (int r = 0; r < RR; ++r) u[r] = P::scale(u[r], inv);
+    const C rk = P::scale(d, inv);
+    if (tid == 0) P::store(a.R + (size_t)ps * a.ldr + k, a.planeR, rk);
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
       constexpr int s = decltype(sI)::value;
-      const int j = cidx[s];
-      if (j > k && j >= lo && j < hi) {
-        const C rk = P::acc_value(xch_tree<0, NW>(j - lo, false));
-        if (tid == 0) {
-          if (j < a.n)
-            P::store(a.R + (size_t)j * a.ldr + k, a.planeR, rk);
-          else
-            P::store(a.y + k, (size_t)a.n, rk);
-        }
+      if (cidx[s] == ps) {
 #pragma unroll
-        for (int r = 0; r < RR; ++r) P::upd(col[s][r], rk, q[r]);
-      }
-      if (j == norm_col) {
-#pragma unroll
-        for (int r = 0; r < RR; ++r) P::acc_abs2(nacc, col[s][r]);
+        for (int r = 0; r < RR; ++r) P::upd(col[s][r], rk, u[r]);
       }
     });
-    xb ^= 1;
-    flush_publish();
-    if (norm_col != RES_NONE) {
-      xch_put(0, nacc, true);
-      lds_barrier();
-      const Rl s2 = P::acc_value_re(xch_tree<0, NW>(0, true));
-      xb ^= 1;
-      finish_norm(norm_col, s2, q, publish_now);
-    }
+    if (last) store_u(ps);
   }
 
   __device__ __forceinline__ void copy_own(int k, C (&q)[RR]) {
@@ -426,24 +445,24 @@ struct Resident {
       }
     });
   }
-  // Reads this thread's rows of q_k from Q, again until none of this
-  // wave's entries is still RES_EMPTY (so it also serves as the wait of the
-  // critical-path steps, which poll the data instead of the counter).
+  // Reads this thread's rows of column k of Q or U, again until none of
+  // this wave's entries is still RES_EMPTY (so it also serves as the wait
+  // of the critical-path steps, which poll U instead of a counter).
   // Returns false on abort or time-out.
-  __device__ __forceinline__ bool load_q(int k, C (&q)[RR]) {
-    const double *src = a.Q + (size_t)k * a.ldq;
+  __device__ __forceinline__ bool load_col(const double *base, size_t ld, size_t plane, int k, C (&q)[RR]) {
+    const double *src = base + (size_t)k * ld;
     long long t0 = -1;
     while (true) {
       bool miss = false;
 #pragma unroll
       for (int r = 0; r < RR; ++r) {
-        const int i = r * RWG + tid;
+        const int i = row_of(r, RWG);
         q[r] = P::czero();
         if (i < a.m) {
           q[r].re.h = coh_load(src + i);
-          q[r].im.h = coh_load(src + i + a.planeQ);
-          q[r].re.l = coh_load(src + i + 2 * a.planeQ);
-          q[r].im.l = coh_load(src + i + 3 * a.planeQ);
+          q[r].im.h = coh_load(src + i + plane);
+          q[r].re.l = coh_load(src + i + 2 * plane);
+          q[r].im.l = coh_load(src + i + 3 * plane);
           miss = miss || __double_as_longlong(q[r].re.h) == RES_EMPTY ||
                  __double_as_longlong(q[r].im.h) == RES_EMPTY || __double_as_longlong(q[r].re.l) == RES_EMPTY ||
                  __double_as_longlong(q[r].im.l) == RES_EMPTY;
@@ -455,9 +474,9 @@ struct Resident {
       __builtin_amdgcn_s_sleep(1);
     }
   }
-  // Start of the factorisation: RES_EMPTY over the owned columns of Q
-  // (after they have been read: Q may be A), then a grid barrier, so that
-  // no entry of Q is read before it is either empty or final.
+  // Start of the factorisation: RES_EMPTY over the owned columns of Q and
+  // U (after they have been read: Q may be A), then a grid barrier, so that
+  // no entry of Q or U is read before it is either empty or final.
   __device__ __forceinline__ bool mark_empty() {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the columns are in registers
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
@@ -465,13 +484,17 @@ struct Resident {
       const int j = cidx[s];
       if (j < a.n) {
         double *dst = a.Q + (size_t)j * a.ldq;
+        double *dsu = a.U + (size_t)j * a.ldu;
         const double e = __longlong_as_double(RES_EMPTY);
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
           const int i = r * RWG + tid;
           if (i < a.m) {
 #pragma unroll
-            for (int pl = 0; pl < 4; ++pl) coh_store(dst + i + pl * a.planeQ, e);
+            for (int pl = 0; pl < 4; ++pl) {
+              coh_store(dst + i + pl * a.planeQ, e);
+              coh_store(dsu + i + pl * a.planeU, e);
+            }
           }
         }
       }
@@ -557,61 +580,42 @@ struct Resident {
     if (last < 0) return;
     const int kend = last < a.n ? last + 1 : a.n;
 
-    // States: 0 = projections from other workgroups, 1 = factoring an
-    // owned panel, 2 = deferred projections (remote q_kd .. q_{ps-1}, then
-    // the panel's own) onto the later owned columns.
+    // States: 0 = projections from other workgroups, 1 = normalising an
+    // owned column, 2 = deferred projections (q_kd .. q_{ps-1} from Q, then
+    // the column's own q) onto the later owned columns.
     int st = 0, seen = 0, nxt = 0, k = 0;
-    int ps = 0, pe = 0, pa = 0, c = 0, kd = -1, dc = 0;
-    int qk = -1;      // q currently holds q_qk (this thread's rows)
-    int normed = -1;  // column of the current panel already normalised
+    int ps = 0, pe = 0, kd = -1, dc = 0;
+    int qk = -1;       // q currently holds q_qk (this thread's rows)
+    int handed = -1;   // last owned column already copied to U
     C q[RR];
-    // Each pass performs at most one bulk projection (apply) or one
-    // critical-path step (panel_step); both have a single call site so
-    // that the loop body holds one copy of each.
+    // Each pass performs one bulk projection (apply), one look-ahead
+    // projection or one normalisation; each has a single call site so that
+    // the loop body holds one copy of it.
     while (true) {
-      int mode = 0;  // 0 nothing, 1 apply, 2 panel_step
-      int opk = -1, lo = 0, hi = RES_NONE, ncol = RES_NONE;
-      int qsrc = 3;  // q_opk: 0 wait and load, 1 owned column, 2 load (already seen), 3 none
-      bool pubnow = true;
+      int mode = 0;  // 1 apply, 2 lookahead_step, 3 own_norm
+      int opk = -1, lo = 0;
+      int qsrc = 3;  // q_opk: 0 wait and load from Q, 1 owned column, 2 load from Q (already seen), 3 none, 4 poll U
       if (st == 0) {
         if (k >= kend) break;
         panel(nxt, nq, g, ps, pe);
-        pa = pe < a.n ? pe : a.n;
         if (k == ps) {
           st = 1;
-          c = ps;
           continue;
         }
         opk = k;
-        qsrc = 0;
         if (ps < a.n && k + a.defer >= ps) {
-          // Critical path first: the panel only; the last projection
-          // before the panel also normalises its first column.
+          // Critical path first: the next owned column only.
           if (kd < 0) kd = k;
           mode = 2;
-          lo = ps;
-          hi = pe;
-          if (k + 1 == ps) ncol = ps;
-          pubnow = ps + 1 >= pe;
+          qsrc = 4;
         } else {
           mode = 1;
+          qsrc = 0;
           lo = k + 1;
         }
       } else if (st == 1) {
-        if (normed != c) {
-          mode = 2;  // normalisation only (the first column of the matrix)
-          hi = 0;
-          ncol = c;
-          pubnow = c + 1 >= pe;
-        } else if (c + 1 < pe) {
-          mode = 2;
-          opk = c;
-          qsrc = 1;
-          lo = c + 1;
-          hi = pe;
-          ncol = c + 1 < pa ? c + 1 : RES_NONE;
-          pubnow = c + 2 >= pe;
-        }
+        mode = 3;
+        opk = ps;
       } else {
         mode = 1;
         opk = dc;
@@ -620,50 +624,45 @@ struct Resident {
       }
 
       if (qsrc == 0) {
-        // Bulk projections wait on the counter; critical-path steps poll
-        // q itself, which arrives before its owner's counter moves.
-        if (mode == 1 && !res_wait(a, opk, wave, seen)) return;
-        if (!load_q(opk, q)) return;
+        if (!res_wait(a, opk, wave, seen)) return;
+        if (!load_col(a.Q, a.ldq, a.planeQ, opk, q)) return;
       } else if (qsrc == 1) {
         if (qk != opk) copy_own(opk, q);
       } else if (qsrc == 2) {
-        if (!load_q(opk, q)) return;  // already seen: returns at once
+        if (!load_col(a.Q, a.ldq, a.planeQ, opk, q)) return;  // already published
+      } else if (qsrc == 4) {
+        if (!load_col(a.U, a.ldu, a.planeU, opk, q)) return;
       }
-      if (qsrc != 3) qk = opk;
       if (mode == 1) {
-        apply(q, opk, lo, hi);
+        apply(q, opk, lo, RES_NONE);
       } else if (mode == 2) {
-        panel_step(q, opk, lo, hi, ncol, pubnow);
-        if (ncol != RES_NONE) {
-          normed = ncol;
-          qk = ncol;
-        }
+        lookahead_step(q, opk, ps, opk + 1 == ps);
+        if (opk + 1 == ps) handed = ps;
+      } else if (mode == 3) {
+        // U[ps] is due unless the last projection was a look-ahead step
+        // (not so for column 0, or when q_{ps-1} is this workgroup's own
+        // and reached column ps as a deferred projection).
+        if (handed != ps) store_u(ps);
+        own_norm(ps, q);
       }
+      qk = opk;
 
       if (st == 0) {
         ++k;
-        if (k == ps && ps < a.n) {
-          st = 1;
-          c = ps;
-        }
+        if (k == ps && ps < a.n) st = 1;
       } else if (st == 1) {
-        if (opk >= 0 || mode == 0) {
-          ++c;
-          if (c >= pa) {
-            if (last >= pe) {
-              st = 2;
-              dc = kd >= 0 ? kd : ps;
-            } else {
-              st = 0;
-              k = pe;
-              ++nxt;
-              kd = -1;
-            }
-          }
+        if (last >= pe) {
+          st = 2;
+          dc = kd >= 0 ? kd : ps;
+        } else {
+          st = 0;
+          k = pe;
+          ++nxt;
+          kd = -1;
         }
       } else {
         ++dc;
-        if (dc >= pa) {
+        if (dc >= pe) {
           st = 0;
           k = pe;
           ++nxt;
@@ -671,7 +670,6 @@ struct Resident {
         }
       }
     }
-    flush_publish();
 
     // rho = ||b - Q y|| after the last projection (Equation (1)).
     if (a.rho != nullptr && last == a.n) {

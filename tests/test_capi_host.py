@@ -44,8 +44,11 @@ def test_status_strings():
 
 
 def test_workspace_sizes():
-    # QR: working copy of b (rounded to 256 bytes) + 1 KiB of sync words
-    assert _lib.workspace_size(32, 32, 2, _lib.MGS_OP_QR) == 2 * 2 * 32 * 8 + 1024
+    # QR: working copy of b (rounded to 256 bytes) + 1 KiB of sync words,
+    # + in dd with m <= 1024 the single launch's hand-off copy of the n
+    # columns (2 L m n doubles)
+    assert _lib.workspace_size(32, 32, 2, _lib.MGS_OP_QR) == 2 * 2 * 32 * 8 + 1024 + 2 * 2 * 32 * 32 * 8
+    assert _lib.workspace_size(1025, 32, 2, _lib.MGS_OP_QR) == 2 * 2 * 1025 * 8 + 1024 + 256 - (2 * 2 * 1025 * 8) % 256
     assert _lib.workspace_size(320, 256, 4, _lib.MGS_OP_QR) == 2 * 4 * 320 * 8 + 1024
     assert _lib.workspace_size(100, 10, 2, _lib.MGS_OP_SOLVE) == 512
     with pytest.raises(_lib.MgsError):
