@@ -522,14 +522,24 @@ __global__ __launch_bounds__(BS_T) void backsolve_blocked_kernel(int n, const do
       }
     }
     __syncthreads();
-    // 3. Rows above the block.
+    // 3. Rows above the block, in the column order of Figure 3; the R
+    // entries of BQ columns are loaded together (one memory latency per
+    // BQ columns instead of per few).
 #pragma unroll
     for (int s = 0; s < NY; ++s) {
       const int j = s * BS_T + tid;
       if (j < k0) {
-#pragma unroll 4
-        for (int c = nb - 1; c >= 0; --c)
-          P::upd(yv[s], P::load(R + (size_t)(k0 + c) * ldr + j, planeR), P::load(xs + c, (size_t)BS_B));
+        constexpr int BQ = (P::L == 4 ? 2 : 8) / NY > 0 ? (P::L == 4 ? 2 : 8) / NY : 1;
+#pragma unroll 1
+        for (int c0 = nb - 1; c0 >= 0; c0 -= BQ) {
+          C rv[BQ];
+#pragma unroll
+          for (int t = 0; t < BQ; ++t)
+            rv[t] = c0 - t >= 0 ? P::load(R + (size_t)(k0 + c0 - t) * ldr + j, planeR) : P::czero();
+#pragma unroll
+          for (int t = 0; t < BQ; ++t)
+            if (c0 - t >= 0) P::upd(yv[s], rv[t], P::load(xs + c0 - t, (size_t)BS_B));
+        }
       }
     }
     __syncthreads();

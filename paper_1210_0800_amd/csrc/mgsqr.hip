@@ -488,7 +488,7 @@ int res_launch_dd(const StepArgs &s, void *sync, double *u, hipStream_t st) {
   a.np = pl.np;
   a.G = pl.G;
   a.xcd_group = pl.G % 8 == 0 ? pl.G / 8 : 0;
-  a.defer = 16;
+  a.defer = 12;
   a.spin_ticks = d.wclk_khz * 2000;  // 2 s
   if (pl.rr == 2) return res_launch_rr<P, 2, 8>(a, d.cus, st);
   switch (pl.nw) {
