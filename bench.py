@@ -230,6 +230,78 @@ def paper_context(torch, api, solves=2000):
     return out
 
 
+def _rate(torch, fn, reps, warm=5):
+    """Calls per second of fn() back to back on the current stream."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return reps / (e0.elapsed_time(e1) * 1e-3)
+
+
+def workloads(torch, api):
+    """The other configurations of the workload table, each with its own
+    protocol: dd 32 x 32 (10,000 back-to-back solves, as the paper times its
+    small systems), qd 320 x 256 overdetermined (200 back-to-back solves),
+    and dd 512 x 384 with the adjoint (forward and backward timed apart)."""
+    from paper_1210_0800_amd import inputs
+
+    dev = torch.device("cuda:0")
+    out = {}
+
+    def solver(d, prec):
+        A, b = torch.from_numpy(d["A"]).to(dev), torch.from_numpy(d["b"]).to(dev)
+        m, n = d["m"], d["n"]
+        Q = torch.empty_like(A)
+        R = torch.empty((prec, 2, n, n), dtype=torch.float64, device=dev)
+        y = torch.empty((prec, 2, n), dtype=torch.float64, device=dev)
+        x = torch.empty_like(y)
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+        info2 = torch.empty(1, dtype=torch.int32, device=dev)
+        work = api.workspace(m, n, prec, 0, dev)
+
+        def one():
+            api.mgs_qr(A, b, Q=Q, R=R, y=y, info=info, work=work, with_rho=False)
+            api.ls_backsolve(R, y, x=x, info=info2)
+
+        return one, (A, b, Q, R, x, info, info2)
+
+    d1 = inputs.config1()
+    one, _ = solver(d1, 2)
+    r1 = _rate(torch, one, 10000)
+    out["dd_32x32"] = {"solves_per_s": r1, "protocol": "10000 back-to-back solves (MGS on [A b] + back substitution)"}
+    print("bench: workload dd 32x32: %.0f solves/s" % r1, file=sys.stderr, flush=True)
+
+    d2 = inputs.config2()
+    one, _ = solver(d2, 4)
+    r2 = _rate(torch, one, 200)
+    out["qd_320x256"] = {"solves_per_s": r2, "protocol": "200 back-to-back solves, noise 1e-40"}
+    print("bench: workload qd 320x256: %.0f solves/s" % r2, file=sys.stderr, flush=True)
+
+    d5 = inputs.config5()
+    one, (A, b, Q, R, x, info, info2) = solver(d5, 2)
+    fwd = _rate(torch, one, 200)
+    g = torch.from_numpy(d5["g"]).to(dev)
+    gA, gb = torch.empty_like(A), torch.empty_like(b)
+    ia = torch.empty(1, dtype=torch.int32, device=dev)
+    wa = api.workspace(d5["m"], d5["n"], 2, 2, dev)
+
+    def back():
+        api.ls_adjoint(A, b, Q, R, x, g, gA=gA, gb=gb, info=ia, work=wa)
+
+    bwd = _rate(torch, back, 200)
+    out["dd_512x384_adjoint"] = {"forward_ms": 1e3 / fwd, "backward_ms": 1e3 / bwd,
+                                 "protocol": "200 forward solves, then 200 adjoint evaluations (dL/dA, dL/db)"}
+    print("bench: workload dd 512x384: forward %.3f ms, backward %.3f ms" % (1e3 / fwd, 1e3 / bwd),
+          file=sys.stderr, flush=True)
+    return out
+
+
 def copy_probe(nbytes):
     import torch
 
@@ -261,7 +333,8 @@ def main():
 
         from paper_1210_0800_amd import api
 
-        print(json.dumps({"paper_context": paper_context(torch, api)}), flush=True)
+        print(json.dumps({"paper_context": paper_context(torch, api), "workloads": workloads(torch, api)}),
+              flush=True)
         return
     if args.only_precision_form:
         import torch
@@ -367,6 +440,7 @@ def main():
     if not args.no_precision_form:
         out["precision_form"] = precision_form(torch, api)
         out["paper_context"] = paper_context(torch, api)
+        out["workloads"] = workloads(torch, api)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host[:4])
     print(json.dumps(out), flush=True)
