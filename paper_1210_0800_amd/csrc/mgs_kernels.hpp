@@ -184,7 +184,7 @@ __device__ __forceinline__ void block_reduce(typename P::Acc (&acc)[BWM], int c_
 // Thread tid holds rows i = r*WG + tid (r < RP) of the panel's columns;
 // rows beyond m are zero, so the inner loops carry no bounds tests.
 template <class P, int RP, int BWM>
-__device__ void panel_role(const StepArgs &a, typename P::Acc *lds, double *qs) {
+__device__ __forceinline__ void panel_role(const StepArgs &a, typename P::Acc *lds, double *qs) {
   using C = typename P::C;
   using Acc = typename P::Acc;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -311,7 +311,7 @@ __device__ void panel_role(const StepArgs &a, typename P::Acc *lds, double *qs) 
 // A team of TW waves owns column j; lane holds rows
 // i = (r*TW + tw_i)*64 + lane, r < RPT (rows beyond m zero).
 template <class P, int RPT, int TW>
-__device__ void trailing_role(const StepArgs &a, int blk, typename P::Acc *lds, double *qs) {
+__device__ __forceinline__ void trailing_role(const StepArgs &a, int blk, typename P::Acc *lds, double *qs) {
   using C = typename P::C;
   using Acc = typename P::Acc;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
