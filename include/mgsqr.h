@@ -101,11 +101,14 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
  *             32 m n bytes).
  *   info      device int, see above.
  * Requires 1 <= n <= m <= MGS_MAX_ROWS_{DD,QD}.
- * Schedule: in dd, when every column fits in the register file of the
- * device (m <= 1024 and at most 5 columns per compute unit, 8 when m <= 512,
- * e.g. 1024 x 1024 with b on 256 compute units) the factorisation is one
- * cooperative launch with the columns held in registers; otherwise (and in
- * qd) one launch per panel of columns.
+ * Schedule: in dd with m <= 64 and at most 64 columns of [A b], one
+ * workgroup (a column per wave slot, q vectors through LDS); in dd when
+ * every column fits in the register file of the device (m <= 1024 and at
+ * most 5 columns per compute unit, 8 when m <= 512, e.g. 1024 x 1024 with b
+ * on 256 compute units) one cooperative launch with the columns held in
+ * registers; otherwise (and in qd) one launch per panel of columns.  The
+ * environment variable MGSQR_SCHEDULE = small | resident | panel forces one
+ * of them (MGS_ERR_DIMS when the forced one does not apply).
  * Both schedules apply the projections of Figure 1 in the same order per
  * column; reduction trees differ, and in the single launch the last two
  * projections onto each column use r_kj = (a_k^H a_j) / r_kk with a_k

@@ -13,6 +13,7 @@
 #include "mgs_kernels.hpp"
 #include "precision_kernels.hpp"
 #include "resident_kernels.hpp"
+#include "small_kernels.hpp"
 
 using namespace mgsq;
 
@@ -508,7 +509,36 @@ int schedule_mode() {
   if (e == nullptr) return 0;
   if (std::strcmp(e, "panel") == 0) return 1;
   if (std::strcmp(e, "resident") == 0) return 2;
+  if (std::strcmp(e, "small") == 0) return 3;
   return 0;
+}
+
+// dd systems of at most SMALL_MAX_ROWS rows and SMALL_MAX_COLS columns of
+// [A b]: one workgroup (returns 1 when the shape does not apply).
+int small_launch_dd(const StepArgs &s, hipStream_t st) {
+  if (s.m > SMALL_MAX_ROWS || s.ncols > SMALL_MAX_COLS) return 1;
+  DevInfo d;
+  if (!dev_info(d)) return 1;
+  SmallArgs a;
+  a.m = s.m;
+  a.n = s.n;
+  a.ncols = s.ncols;
+  a.A = s.A;
+  a.lda = s.lda;
+  a.planeA = s.planeA;
+  a.b = s.b;
+  a.Q = s.Q;
+  a.ldq = s.ldq;
+  a.planeQ = s.planeQ;
+  a.R = s.R;
+  a.ldr = s.ldr;
+  a.planeR = s.planeR;
+  a.y = s.y;
+  a.rho = s.rho;
+  a.info = s.info;
+  a.spin_ticks = d.wclk_khz * 2000;  // 2 s
+  hipLaunchKernelGGL(mgs_small_kernel, dim3(1), dim3(64 * SMALL_WAVES), 0, st, a);
+  return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
 }
 
 }  // namespace
@@ -579,7 +609,12 @@ int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq,
   a.init_info = 1;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int mode = schedule_mode();
-  if (mode != 1) {
+  if (mode == 0 || mode == 3) {
+    const int rc = prec == 2 ? small_launch_dd(a, st) : 1;
+    if (rc != 1) return rc;
+    if (mode == 3) return MGS_ERR_DIMS;
+  }
+  if (mode == 0 || mode == 2) {
     void *sync = static_cast<char *>(work) + qr_w_bytes(m, prec);
     double *u = reinterpret_cast<double *>(static_cast<char *>(sync) + sizeof(unsigned int) * RES_SYNC_WORDS);
     const int rc = prec == 2 && qr_u_bytes(m, n, prec) > 0 ? res_launch_dd(a, sync, u, st) : 1;

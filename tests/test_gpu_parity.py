@@ -121,9 +121,39 @@ def test_qd_random_parity(m, n):
     check_case(p["A"], p["b"], 4, invariants=(m * n <= 100 * 100), schedules=("auto", "panel"))
 
 
+SMALL_SHAPES = [(1, 1), (5, 1), (17, 16), (32, 32), (33, 7), (64, 40), (64, 63)]
+
+
+@pytest.mark.parametrize("m,n", SMALL_SHAPES)
+def test_dd_small_schedule_parity(m, n):
+    """The one-workgroup schedule (dd, m <= 64, at most 64 columns of [A b])
+    against the oracle, and against the single-launch schedule."""
+    p = inputs.random_problem(2, m, n, seed=m * 5 + n, config=54)
+    e, g, o = check_case(p["A"], p["b"], 2, invariants=True, schedules=("small", "resident"))
+    print("small %dx%d" % (m, n), e)
+
+
+def test_dd_small_schedule_in_place_and_refusals():
+    from paper_1210_0800_amd import _lib
+
+    p = inputs.random_problem(2, 40, 30, seed=11, config=55)
+    with schedule("small"):
+        f = api.mgs_qr(T(p["A"]))
+        Q1, R1 = N(f["Q"]), N(f["R"])
+        Ain = T(p["A"])
+        f2 = api.mgs_qr(Ain, Q=Ain)
+        torch.cuda.synchronize()
+        assert np.array_equal(N(Ain), Q1) and np.array_equal(N(f2["R"]), R1)
+        for prec, m, n in ((2, 65, 20), (2, 64, 64), (4, 32, 32)):
+            q = inputs.random_problem(prec, m, n, seed=3, config=55)
+            with pytest.raises(_lib.MgsError) as err:
+                api.mgs_qr(T(q["A"]), T(q["b"]))
+            assert err.value.status == -1
+
+
 def test_config1_dd_32x32():
     d = inputs.config1()
-    e, g, o = check_case(d["A"], d["b"], 2, invariants=True)
+    e, g, o = check_case(d["A"], d["b"], 2, invariants=True, schedules=("auto", "resident"))
     # consistent square system: x_true recovered
     dx = np.abs((g["x"][0] + g["x"][1]) - (d["x_true"][0] + d["x_true"][1]))
     assert dx.max() <= 1e-27 * e["kappa"]
