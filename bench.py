@@ -344,7 +344,7 @@ def main():
         print(json.dumps({"precision_form": precision_form(torch, api)}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+        print("bench.py: one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
