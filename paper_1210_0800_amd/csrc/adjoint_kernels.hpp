@@ -12,26 +12,40 @@
 namespace mgsq {
 
 // w = R^{-H} g, column oriented: for k = 0..n-1, w_k = g_k / r_kk, then
-// g_j -= conj(r_kj) w_k for j > k.  One block; thread tid keeps g_j for
-// j = s*WG + tid; the row k+1 of R is fetched while step k is in progress.
+// g_j -= conj(r_kj) w_k for j > k (the lower-triangular counterpart of the
+// back substitution of Figure 3).  Blocked like backsolve_blocked_kernel,
+// from the top: one workgroup of BS_T threads, thread t holding g_j for
+// j = s*BS_T + t; for each block [k0, k0 + B) of columns
+//   1. its upper triangle of R is staged in LDS;
+//   2. the wave holding rows k0 .. k0+B-1 solves it: w_k = g_k / r_kk
+//      (owner lane), broadcast by readlane, g_j -= conj(r_kj) w_k for the
+//      block rows j > k;
+//   3. every thread with j >= k0 + B applies g_j -= conj(r_kj) w_k for the
+//      block's k in ascending order (its R entries are consecutive in
+//      memory, read BQ at a time).
+// Each g_j receives conj(r_kj) w_k in the order k = 0, 1, ..., j-1 with the
+// operations of the column-oriented loop, so w is bitwise that loop's.
 template <class P, int NY>
-__global__ __launch_bounds__(WG) void fwdsub_kernel(int n, const double *R, int ldr, size_t planeR,
-                                                     const double *g, double *w, int *info) {
+__global__ __launch_bounds__(BS_T) void fwdsub_blocked_kernel(int n, const double *R, int ldr, size_t planeR,
+                                                              const double *g, double *w, int *info) {
   using C = typename P::C;
   using Rl = typename P::R;
-  __shared__ C ws[2];
+  constexpr int NP = 2 * P::L;
+  constexpr int BS_B = bs_block(P::L);
+  __shared__ double rb[NP * BS_B * BS_B];  // block of R, planar [p][col][row]
+  __shared__ double xs[NP * BS_B];         // w of the block, planar [p][k]
   __shared__ int bad;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   if (tid == 0) bad = 0x7fffffff;
   __syncthreads();
   C gv[NY];
   Rl inv[NY];
 #pragma unroll
   for (int s = 0; s < NY; ++s) {
-    int j = s * WG + tid;
+    const int j = s * BS_T + tid;
     if (j < n) {
       gv[s] = P::load(g + j, (size_t)n);
-      C d = P::load(R + (size_t)j * ldr + j, planeR);
+      const C d = P::load(R + (size_t)j * ldr + j, planeR);
       if (!P::ok_norm(d.re)) atomicMin(&bad, j + 1);
       inv[s] = P::recip(d.re);
     } else {
@@ -40,41 +54,63 @@ __global__ __launch_bounds__(WG) void fwdsub_kernel(int n, const double *R, int 
     }
   }
   __syncthreads();
-  if (tid == 0) *info = (bad == 0x7fffffff) ? 0 : bad;
-  // rk[s] = R(k, j) for the current k (row k of R, strided in memory)
-  C rk[NY];
-#pragma unroll
-  for (int s = 0; s < NY; ++s) {
-    int j = s * WG + tid;
-    rk[s] = (j > 0 && j < n) ? P::load(R + (size_t)j * ldr + 0, planeR) : P::czero();
-  }
+  if (tid == 0 && info != nullptr) *info = (bad == 0x7fffffff) ? 0 : bad;
+  const int nblk = (n + BS_B - 1) / BS_B;
 #pragma unroll 1
-  for (int k = 0; k < n; ++k) {
-    const int sk = k / WG, owner = k - sk * WG;
-    C rn[NY];
-#pragma unroll
-    for (int s = 0; s < NY; ++s) {
-      int j = s * WG + tid;
-      rn[s] = (j > k + 1 && j < n) ? P::load(R + (size_t)j * ldr + (k + 1), planeR) : P::czero();
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = kb * BS_B;
+    const int k1 = k0 + BS_B < n ? k0 + BS_B : n;
+    const int nb = k1 - k0;
+    // 1. R(k0 + r, k0 + c) for r <= c < nb into LDS.
+    for (int e = tid; e < BS_B * BS_B; e += BS_T) {
+      const int c = e / BS_B, r = e - c * BS_B;
+      if (c < nb && r <= c) {
+        const C v = P::load(R + (size_t)(k0 + c) * ldr + (k0 + r), planeR);
+        P::store(rb + c * BS_B + r, (size_t)BS_B * BS_B, v);
+      }
     }
-    if (tid == owner) {
+    __syncthreads();
+    // 2. The wave holding rows k0 .. k1-1 (one slot s, consecutive lanes).
+    const int sk = k0 / BS_T, tk = k0 - sk * BS_T;
+    if (wave == tk / 64) {
+      const int l0 = tk % 64;
 #pragma unroll
       for (int s = 0; s < NY; ++s) {
         if (s == sk) {
-          C wk = P::scale(gv[s], inv[s]);
-          P::store(w + k, (size_t)n, wk);
-          ws[k & 1] = wk;
+          const int i = lane - l0;  // block row of this lane
+#pragma unroll 1
+          for (int c = 0; c < nb; ++c) {
+            const C xl = P::scale(gv[s], inv[s]);
+            const C xk = bs_readlane<P>(xl, l0 + c);
+            if (i == c) {
+              P::store(w + k0 + c, (size_t)n, xk);
+              P::store(xs + c, (size_t)BS_B, xk);
+            }
+            if (i > c && i < nb) P::upd(gv[s], P::conj(P::load(rb + i * BS_B + c, (size_t)BS_B * BS_B)), xk);
+          }
         }
       }
     }
     __syncthreads();
-    const C wk = ws[k & 1];
+    // 3. Rows below the block.
 #pragma unroll
     for (int s = 0; s < NY; ++s) {
-      int j = s * WG + tid;
-      if (j > k && j < n) P::upd(gv[s], P::conj(rk[s]), wk);
-      rk[s] = rn[s];
+      const int j = s * BS_T + tid;
+      if (j >= k1 && j < n) {
+        constexpr int BQ = (P::L == 4 ? 2 : 8) / NY > 0 ? (P::L == 4 ? 2 : 8) / NY : 1;
+        const double *rj = R + (size_t)j * ldr + k0;
+#pragma unroll 1
+        for (int c0 = 0; c0 < nb; c0 += BQ) {
+          C rv[BQ];
+#pragma unroll
+          for (int t = 0; t < BQ; ++t) rv[t] = c0 + t < nb ? P::load(rj + c0 + t, planeR) : P::czero();
+#pragma unroll
+          for (int t = 0; t < BQ; ++t)
+            if (c0 + t < nb) P::upd(gv[s], P::conj(rv[t]), P::load(xs + c0 + t, (size_t)BS_B));
+        }
+      }
     }
+    __syncthreads();
   }
 }
 

@@ -196,18 +196,16 @@ size_t adjoint_work_bytes(int m, int n, int prec) {
 
 template <class P>
 int fwdsub_launch(int n, const double *R, int ldr, const double *g, double *w, int *info, hipStream_t st) {
-  const int ny = pow2_at_least(ceil_div(n, WG));
+  const int ny = pow2_at_least(ceil_div(n, BS_T));
   const size_t planeR = (size_t)ldr * n;
-#define MGS_FS_CASE(NYV)                                                                                 \
-  case NYV:                                                                                              \
-    hipLaunchKernelGGL((fwdsub_kernel<P, NYV>), dim3(1), dim3(WG), 0, st, n, R, ldr, planeR, g, w, info); \
+#define MGS_FS_CASE(NYV)                                                                                       \
+  case NYV:                                                                                                    \
+    hipLaunchKernelGGL((fwdsub_blocked_kernel<P, NYV>), dim3(1), dim3(BS_T), 0, st, n, R, ldr, planeR, g, w, info); \
     break;
   switch (ny) {
     MGS_FS_CASE(1)
     MGS_FS_CASE(2)
     MGS_FS_CASE(4)
-    MGS_FS_CASE(8)
-    MGS_FS_CASE(16)
     default:
       return MGS_ERR_DIMS;
   }
