@@ -104,6 +104,18 @@ __device__ __forceinline__ int row_of(int r, int rwg) {
   return i;
 }
 
+// info = the smallest 1-based column with a zero or non-finite norm (the
+// owner of a later column can get there first, since it does not wait for
+// the earlier column's normalisation); a negative status is kept.
+__device__ __forceinline__ void info_first_bad(int *info, int v) {
+  int old = __hip_atomic_load(info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (old == 0 || old > v) {
+    const int prev = atomicCAS(info, old, v);
+    if (prev == old) break;
+    old = prev;
+  }
+}
+
 // Common end of a bounded wait: true (and the abort flag set, info
 // written) once the wall-clock limit has passed, or when another wave has
 // aborted.
@@ -356,7 +368,7 @@ struct Resident {
     lds_barrier();
     const Rl s2 = P::acc_value_re(xch_tree<0, NW>(0, true));
     xb ^= 1;
-    if (!P::ok_norm(s2) && tid == 0) atomicCAS(a.info, 0, x + 1);
+    if (!P::ok_norm(s2) && tid == 0) info_first_bad(a.info, x + 1);
     Rl rkk, inv;
     P::sqrt_recip(s2, rkk, inv);
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {

@@ -231,6 +231,20 @@ def test_zero_column_and_zero_pivot_report_info():
     assert int(info.item()) == 3
 
 
+@pytest.mark.parametrize("m,n,sched", [(48, 30, "small"), (48, 30, "resident"), (48, 30, "panel"),
+                                       (300, 200, "resident")])
+def test_non_finite_column_reports_first(m, n, sched):
+    """A NaN in column 7 and a zero column 12: info names column 8 (the
+    first bad one, 1-based) on every schedule, and the run ends normally
+    (the hand-offs carry NaNs without stalling)."""
+    p = inputs.random_problem(2, m, n, seed=8, config=57)
+    A = p["A"].copy()
+    A[0, 0, 7, 3] = np.nan
+    A[:, :, 12] = 0.0
+    g = gpu_lstsq(A, p["b"], sched)
+    assert int(g["info"][0]) == 8, sched
+
+
 @pytest.mark.parametrize("sched", ["auto", "panel"])
 def test_reproducible_bitwise(sched):
     p = inputs.random_problem(2, 700, 400, seed=5, config=56)
