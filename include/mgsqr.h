@@ -55,10 +55,10 @@ enum {
   MGS_OK = 0,
   MGS_ERR_DIMS = -1,        /* n < 1, m < n, ld too small, size above the supported maximum */
   MGS_ERR_POINTER = -2,     /* required pointer NULL or not 8-byte aligned, forbidden aliasing */
-  MGS_ERR_PREC = -3,        /* prec not 2 or 4 */
+  MGS_ERR_PREC = -3,        /* prec not supported by the entry point, or block not 64 */
   MGS_ERR_WORKSPACE = -4,   /* work_bytes below mgs_workspace_size() */
   MGS_ERR_LAUNCH = -5,      /* a kernel launch failed (HIP error) */
-  MGS_ERR_UNSUPPORTED = -6  /* unknown operation code */
+  MGS_ERR_UNSUPPORTED = -6  /* unknown operation code or schedule */
 };
 
 /* *info value of a factorisation whose inter-workgroup wait timed out. */
@@ -106,11 +106,10 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
  * every column fits in the register file of the device (m <= 1024 and at
  * most 5 columns per compute unit, 8 when m <= 512, e.g. 1024 x 1024 with b
  * on 256 compute units) one cooperative launch with the columns held in
- * registers; otherwise (and in qd) one launch per panel of columns.  The
- * environment variable MGSQR_SCHEDULE = small | resident | panel forces one
- * of them (MGS_ERR_DIMS when the forced one does not apply).
- * Both schedules apply the projections of Figure 1 in the same order per
- * column; reduction trees differ, and in the single launch the last two
+ * registers; otherwise (and in qd) one launch per panel of columns.
+ * mgs_qr_schedule (below) forces one of them.
+ * All schedules apply the projections of Figure 1 in the same order per
+ * column; reduction trees differ, and in the single launch the last twelve
  * projections onto each column use r_kj = (a_k^H a_j) / r_kk with a_k
  * before its normalisation (equal to q_k^H a_j in exact arithmetic), so
  * results agree to rounding.
@@ -118,6 +117,22 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
 int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq, double *R, int ldr,
            const double *b, double *y, double *rho, void *work, size_t work_bytes, int *info,
            mgs_stream_t stream);
+
+/* Schedules of mgs_qr_schedule. */
+enum { MGS_SCHED_AUTO = 0, MGS_SCHED_PANEL = 1, MGS_SCHED_RESIDENT = 2, MGS_SCHED_SMALL = 3 };
+
+/*
+ * mgs_qr_schedule -- mgs_qr with the schedule named by the caller (for
+ * tests and diagnostics; mgs_qr is this call with MGS_SCHED_AUTO):
+ * MGS_SCHED_PANEL one launch per panel, MGS_SCHED_RESIDENT the single
+ * cooperative launch, MGS_SCHED_SMALL the one-workgroup schedule.
+ * Returns MGS_ERR_DIMS when the named schedule does not apply to the
+ * shape and precision, MGS_ERR_UNSUPPORTED for an unknown schedule;
+ * otherwise as mgs_qr.
+ */
+int mgs_qr_schedule(int m, int n, int prec, const double *A, int lda, double *Q, int ldq, double *R, int ldr,
+                    const double *b, double *y, double *rho, void *work, size_t work_bytes, int *info,
+                    int schedule, mgs_stream_t stream);
 
 /*
  * ls_solve -- least-squares solution x of A x = b from the MGS factors of
@@ -178,7 +193,7 @@ int ls_adjoint(int m, int n, int prec, const double *A, int lda, const double *b
  *      stalled; that d is not applied): converged to the attainable accuracy
  *      if the last applied ||d|| / ||x|| <= sqrt(tol), stagnation otherwise.
  *   A [in] m x n planar (lda), b [in] m planar, x [out] n planar, all in
- *   `prec` limbs.  block must be 64.  tol >= 0 (e.g. 2^-104 dd, 2^-209 qd).
+ *   `prec` limbs.  block must be 64 (MGS_ERR_PREC otherwise).  tol >= 0 (e.g. 2^-104 dd, 2^-209 qd).
  *   iters [out, device int or NULL]: refinement steps applied.
  *   err_est [out, device double or NULL]: ||d|| / ||x|| of the last step.
  *   work: mgs_workspace_size(m, n, prec, MGS_OP_REFINE) bytes.
@@ -207,7 +222,7 @@ int mgs_refine_solve(int m, int n, int prec, const double *A, int lda, const dou
  *             upper triangular, real positive diagonal, lower triangle 0.
  *   y  [out]  n planar: y = Q^H b as the projections of b (required when
  *             b != NULL, ignored otherwise).
- *   block     panel width; must be 64.
+ *   block     panel width; must be 64 (MGS_ERR_PREC otherwise).
  *   work      mgs_workspace_size(m, n, 1, MGS_OP_QR64, .) bytes.
  *   info      device int: 0, or k > 0 when column k had a zero or
  *             non-finite norm.

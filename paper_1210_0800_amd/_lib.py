@@ -18,8 +18,9 @@ MGS_OP_REFINE = 3
 MGS_OP_QR64 = 4
 MGS_MAX_ROWS = {2: 4096, 4: 2048}
 
-EXPORTS = ("mgs_abi_version", "mgs_status_string", "mgs_workspace_size", "mgs_qr", "ls_solve",
-           "ls_backsolve", "ls_adjoint", "mgs_refine_solve", "mgs_qr64")
+EXPORTS = ("mgs_abi_version", "mgs_status_string", "mgs_workspace_size", "mgs_qr", "mgs_qr_schedule",
+           "ls_solve", "ls_backsolve", "ls_adjoint", "mgs_refine_solve", "mgs_qr64")
+SCHEDULES = {"auto": 0, "panel": 1, "resident": 2, "small": 3}
 
 _lib = None
 
@@ -47,6 +48,8 @@ def lib():
         L.mgs_workspace_size.restype = I
         L.mgs_qr.argtypes = [I, I, I, P, I, P, I, P, I, P, P, P, P, S, P, P]
         L.mgs_qr.restype = I
+        L.mgs_qr_schedule.argtypes = [I, I, I, P, I, P, I, P, I, P, P, P, P, S, P, I, P]
+        L.mgs_qr_schedule.restype = I
         L.ls_solve.argtypes = [I, I, I, P, I, P, I, P, P, P, S, P, P]
         L.ls_solve.restype = I
         L.ls_backsolve.argtypes = [I, I, P, I, P, P, P, P]

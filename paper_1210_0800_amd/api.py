@@ -18,15 +18,34 @@ def _stream(t):
     return torch.cuda.current_stream(t.device).cuda_stream
 
 
-def _check_planar(name, t, prec=None, ndim=None):
+def _check_planar(name, t, prec=None, ndim=None, shape=None, device=None):
+    """t must be a contiguous float64 device tensor; shape (when given) is
+    its full expected shape, so that no kernel reads or writes past it."""
     if not isinstance(t, torch.Tensor):
         raise TypeError("%s must be a torch.Tensor" % name)
     if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
         raise ValueError("%s must be a contiguous float64 tensor on a HIP device" % name)
+    if device is not None and t.device != device:
+        raise ValueError("%s must be on %s, got %s" % (name, device, t.device))
     if ndim is not None and t.dim() != ndim:
         raise ValueError("%s must have %d dimensions, got shape %s" % (name, ndim, tuple(t.shape)))
-    if t.shape[1] != 2 or (prec is not None and t.shape[0] != prec):
+    if t.dim() < 2 or t.shape[1] != 2 or (prec is not None and t.shape[0] != prec):
         raise ValueError("%s must have shape [prec, 2, ...], got %s" % (name, tuple(t.shape)))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+
+
+def _check_info(info, device):
+    if not isinstance(info, torch.Tensor) or info.dtype != torch.int32 or info.numel() < 1 or \
+            info.device != device or not info.is_contiguous():
+        raise ValueError("info must be a contiguous int32 tensor on %s" % device)
+
+
+def _check_work(work, nbytes, device):
+    if not isinstance(work, torch.Tensor) or not work.is_contiguous() or work.device != device:
+        raise ValueError("work must be a contiguous tensor on %s" % device)
+    if work.numel() * work.element_size() < nbytes:
+        raise ValueError("work holds %d bytes, %d needed" % (work.numel() * work.element_size(), nbytes))
 
 
 def workspace(m, n, prec, op, device):
@@ -34,36 +53,47 @@ def workspace(m, n, prec, op, device):
     return torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=device)
 
 
-def mgs_qr(A, b=None, *, Q=None, R=None, y=None, rho=None, info=None, work=None, with_rho=True):
+def mgs_qr(A, b=None, *, Q=None, R=None, y=None, rho=None, info=None, work=None, with_rho=True,
+           schedule=None):
     """MGS QR of A (Figure 1), of [A b] when b is given (Equation (1)).
 
     Returns dict(Q, R, y, rho, info) of device tensors; Q may be passed as A
-    itself to factor in place.
+    itself to factor in place.  schedule (None = automatic) names one of
+    "panel", "resident", "small" (mgs_qr_schedule; for tests and timing).
     """
     _check_planar("A", A, ndim=4)
     prec, _, n, m = A.shape
     dev = A.device
     Q = torch.empty_like(A) if Q is None else Q
-    _check_planar("Q", Q, prec, 4)
-    if tuple(Q.shape) != tuple(A.shape):
-        raise ValueError("Q must have the shape of A")
+    _check_planar("Q", Q, prec, 4, shape=A.shape, device=dev)
     R = torch.empty((prec, 2, n, n), dtype=torch.float64, device=dev) if R is None else R
-    _check_planar("R", R, prec, 4)
+    _check_planar("R", R, prec, 4, shape=(prec, 2, n, n), device=dev)
     info = torch.empty(1, dtype=torch.int32, device=dev) if info is None else info
+    _check_info(info, dev)
     if b is not None:
-        _check_planar("b", b, prec, 3)
-        if b.shape[2] != m:
-            raise ValueError("b must have m = %d rows" % m)
+        _check_planar("b", b, prec, 3, shape=(prec, 2, m), device=dev)
         y = torch.empty((prec, 2, n), dtype=torch.float64, device=dev) if y is None else y
+        _check_planar("y", y, prec, 3, shape=(prec, 2, n), device=dev)
         if with_rho and rho is None:
             rho = torch.empty(prec, dtype=torch.float64, device=dev)
+        if rho is not None and (not isinstance(rho, torch.Tensor) or rho.dtype != torch.float64 or
+                                rho.numel() != prec or rho.device != dev or not rho.is_contiguous()):
+            raise ValueError("rho must be a contiguous float64 tensor of %d limbs on %s" % (prec, dev))
     else:
         y = rho = None
+    nwork = _lib.workspace_size(m, n, prec, _lib.MGS_OP_QR)
     work = workspace(m, n, prec, _lib.MGS_OP_QR, dev) if work is None else work
+    _check_work(work, nwork, dev)
     nwork = work.numel() * work.element_size()
-    st = _lib.lib().mgs_qr(m, n, prec, _ptr(A), m, _ptr(Q), m, _ptr(R), R.shape[3], _ptr(b), _ptr(y),
-                           _ptr(rho), _ptr(work), nwork, _ptr(info), _stream(A))
-    _lib.check("mgs_qr", st)
+    if schedule is None:
+        st = _lib.lib().mgs_qr(m, n, prec, _ptr(A), m, _ptr(Q), m, _ptr(R), n, _ptr(b), _ptr(y),
+                               _ptr(rho), _ptr(work), nwork, _ptr(info), _stream(A))
+        _lib.check("mgs_qr", st)
+    else:
+        st = _lib.lib().mgs_qr_schedule(m, n, prec, _ptr(A), m, _ptr(Q), m, _ptr(R), n, _ptr(b), _ptr(y),
+                                        _ptr(rho), _ptr(work), nwork, _ptr(info), _lib.SCHEDULES[schedule],
+                                        _stream(A))
+        _lib.check("mgs_qr_schedule", st)
     return dict(Q=Q, R=R, y=y, rho=rho, info=info)
 
 
@@ -71,9 +101,14 @@ def ls_backsolve(R, y, *, x=None, info=None):
     """x = R^-1 y by the column-oriented back substitution of Figure 3."""
     _check_planar("R", R, ndim=4)
     prec, _, n, ldr = R.shape
-    _check_planar("y", y, prec, 3)
+    dev = R.device
+    if ldr != n:
+        raise ValueError("R must be square, got %s" % (tuple(R.shape),))
+    _check_planar("y", y, prec, 3, shape=(prec, 2, n), device=dev)
     x = torch.empty_like(y) if x is None else x
-    info = torch.empty(1, dtype=torch.int32, device=R.device) if info is None else info
+    _check_planar("x", x, prec, 3, shape=(prec, 2, n), device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev) if info is None else info
+    _check_info(info, dev)
     st = _lib.lib().ls_backsolve(n, prec, _ptr(R), ldr, _ptr(y), _ptr(x), _ptr(info), _stream(R))
     _lib.check("ls_backsolve", st)
     return x, info
@@ -83,20 +118,25 @@ def ls_solve(Q, R, b, *, x=None, info=None, work=None):
     """x = R^-1 (Q^H b), Q^H b by sequential MGS projections of b."""
     _check_planar("Q", Q, ndim=4)
     prec, _, n, m = Q.shape
-    _check_planar("R", R, prec, 4)
-    _check_planar("b", b, prec, 3)
-    x = torch.empty((prec, 2, n), dtype=torch.float64, device=Q.device) if x is None else x
-    info = torch.empty(1, dtype=torch.int32, device=Q.device) if info is None else info
-    work = workspace(m, n, prec, _lib.MGS_OP_SOLVE, Q.device) if work is None else work
-    st = _lib.lib().ls_solve(m, n, prec, _ptr(Q), m, _ptr(R), R.shape[3], _ptr(b), _ptr(x), _ptr(work),
-                             work.numel() * 8, _ptr(info), _stream(Q))
+    dev = Q.device
+    _check_planar("R", R, prec, 4, shape=(prec, 2, n, n), device=dev)
+    _check_planar("b", b, prec, 3, shape=(prec, 2, m), device=dev)
+    x = torch.empty((prec, 2, n), dtype=torch.float64, device=dev) if x is None else x
+    _check_planar("x", x, prec, 3, shape=(prec, 2, n), device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev) if info is None else info
+    _check_info(info, dev)
+    nwork = _lib.workspace_size(m, n, prec, _lib.MGS_OP_SOLVE)
+    work = workspace(m, n, prec, _lib.MGS_OP_SOLVE, dev) if work is None else work
+    _check_work(work, nwork, dev)
+    st = _lib.lib().ls_solve(m, n, prec, _ptr(Q), m, _ptr(R), n, _ptr(b), _ptr(x), _ptr(work),
+                             work.numel() * work.element_size(), _ptr(info), _stream(Q))
     _lib.check("ls_solve", st)
     return x, info
 
 
-def lstsq(A, b):
+def lstsq(A, b, *, schedule=None):
     """Least-squares solution of A x = b: MGS on [A b], then back substitution."""
-    f = mgs_qr(A, b)
+    f = mgs_qr(A, b, schedule=schedule)
     x, info2 = ls_backsolve(f["R"], f["y"])
     f["x"] = x
     f["info_backsolve"] = info2
@@ -111,16 +151,22 @@ def ls_adjoint(A, b, Q, R, x, gx, *, gA=None, gb=None, info=None, work=None):
     """
     _check_planar("A", A, ndim=4)
     prec, _, n, m = A.shape
-    for name, t, nd in (("b", b, 3), ("Q", Q, 4), ("R", R, 4), ("x", x, 3), ("gx", gx, 3)):
-        _check_planar(name, t, prec, nd)
     dev = A.device
+    for name, t, shp in (("b", b, (prec, 2, m)), ("Q", Q, (prec, 2, n, m)), ("R", R, (prec, 2, n, n)),
+                         ("x", x, (prec, 2, n)), ("gx", gx, (prec, 2, n))):
+        _check_planar(name, t, prec, len(shp), shape=shp, device=dev)
     gA = torch.empty_like(A) if gA is None else gA
     gb = torch.empty_like(b) if gb is None else gb
+    _check_planar("gA", gA, prec, 4, shape=A.shape, device=dev)
+    _check_planar("gb", gb, prec, 3, shape=(prec, 2, m), device=dev)
     info = torch.empty(1, dtype=torch.int32, device=dev) if info is None else info
+    _check_info(info, dev)
+    nwork = _lib.workspace_size(m, n, prec, _lib.MGS_OP_ADJOINT)
     work = workspace(m, n, prec, _lib.MGS_OP_ADJOINT, dev) if work is None else work
-    st = _lib.lib().ls_adjoint(m, n, prec, _ptr(A), m, _ptr(b), _ptr(Q), m, _ptr(R), R.shape[3], _ptr(x),
-                               _ptr(gx), _ptr(gA), m, _ptr(gb), _ptr(work), work.numel() * 8, _ptr(info),
-                               _stream(A))
+    _check_work(work, nwork, dev)
+    st = _lib.lib().ls_adjoint(m, n, prec, _ptr(A), m, _ptr(b), _ptr(Q), m, _ptr(R), n, _ptr(x),
+                               _ptr(gx), _ptr(gA), m, _ptr(gb), _ptr(work), work.numel() * work.element_size(),
+                               _ptr(info), _stream(A))
     _lib.check("ls_adjoint", st)
     return gA, gb, info
 
@@ -161,17 +207,21 @@ def refine_lstsq(A, b, *, tol=None, max_iter=20, x=None, work=None):
     """
     _check_planar("A", A, ndim=4)
     prec, _, n, m = A.shape
-    _check_planar("b", b, prec, 3)
     dev = A.device
+    _check_planar("b", b, prec, 3, shape=(prec, 2, m), device=dev)
     if tol is None:
         tol = 2.0 ** -104 if prec == 2 else 2.0 ** -209
     x = torch.empty((prec, 2, n), dtype=torch.float64, device=dev) if x is None else x
+    _check_planar("x", x, prec, 3, shape=(prec, 2, n), device=dev)
     iters = torch.zeros(1, dtype=torch.int32, device=dev)
     err = torch.zeros(1, dtype=torch.float64, device=dev)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
+    nwork = _lib.workspace_size(m, n, prec, _lib.MGS_OP_REFINE)
     work = workspace(m, n, prec, _lib.MGS_OP_REFINE, dev) if work is None else work
+    _check_work(work, nwork, dev)
     st = _lib.lib().mgs_refine_solve(m, n, prec, _ptr(A), m, _ptr(b), _ptr(x), 64, float(tol), int(max_iter),
-                                     _ptr(iters), _ptr(err), _ptr(work), work.numel() * 8, _ptr(info), _stream(A))
+                                     _ptr(iters), _ptr(err), _ptr(work), work.numel() * work.element_size(),
+                                     _ptr(info), _stream(A))
     _lib.check("mgs_refine_solve", st)
     return dict(x=x, iters=iters, err_est=err, info=info)
 

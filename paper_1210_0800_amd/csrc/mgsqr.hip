@@ -6,8 +6,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <cstdlib>
-#include <cstring>
 
 #include "adjoint_kernels.hpp"
 #include "mgs_kernels.hpp"
@@ -428,6 +426,12 @@ bool res_choose(int m, int ncols, int cus, ResPlan &pl) {
   return false;
 }
 
+#ifdef MGS_TRACE
+// Diagnostic builds: device buffer of RES_TRACE_SLOTS stamps per column for
+// the next single-launch factorisations (mgs_set_trace).
+long long *g_trace = nullptr;
+#endif
+
 // Returns 1 when the single launch does not apply here (the caller then
 // takes the per-panel schedule).
 template <class P, int RR, int NW>
@@ -489,6 +493,9 @@ int res_launch_dd(const StepArgs &s, void *sync, double *u, hipStream_t st) {
   a.xcd_group = pl.G % 8 == 0 ? pl.G / 8 : 0;
   a.defer = 12;
   a.spin_ticks = d.wclk_khz * 2000;  // 2 s
+#ifdef MGS_TRACE
+  a.trace = g_trace;
+#endif
   if (pl.rr == 2) return res_launch_rr<P, 2, 8>(a, d.cus, st);
   switch (pl.nw) {
     case 1: return res_launch_rr<P, 1, 1>(a, d.cus, st);
@@ -497,18 +504,6 @@ int res_launch_dd(const StepArgs &s, void *sync, double *u, hipStream_t st) {
     case 8: return res_launch_rr<P, 1, 8>(a, d.cus, st);
   }
   return 1;
-}
-
-// Schedule override: MGSQR_SCHEDULE=panel forces one launch per panel,
-// =resident requires the single launch (MGS_ERR_DIMS when it does not
-// apply); unset or any other value chooses automatically.
-int schedule_mode() {
-  const char *e = std::getenv("MGSQR_SCHEDULE");
-  if (e == nullptr) return 0;
-  if (std::strcmp(e, "panel") == 0) return 1;
-  if (std::strcmp(e, "resident") == 0) return 2;
-  if (std::strcmp(e, "small") == 0) return 3;
-  return 0;
 }
 
 // dd systems of at most SMALL_MAX_ROWS rows and SMALL_MAX_COLS columns of
@@ -543,6 +538,11 @@ int small_launch_dd(const StepArgs &s, hipStream_t st) {
 
 extern "C" {
 
+#ifdef MGS_TRACE
+// Diagnostic builds only (not declared in the public header).
+void mgs_set_trace(long long *buf) { g_trace = buf; }
+#endif
+
 int mgs_abi_version(void) { return MGS_ABI_VERSION; }
 
 const char *mgs_status_string(int status) {
@@ -550,10 +550,10 @@ const char *mgs_status_string(int status) {
     case MGS_OK: return "success";
     case MGS_ERR_DIMS: return "invalid dimensions (need 1 <= n <= m <= max rows, ld >= rows)";
     case MGS_ERR_POINTER: return "null, misaligned or illegally aliased pointer";
-    case MGS_ERR_PREC: return "unsupported precision (prec must be 2 or 4)";
+    case MGS_ERR_PREC: return "unsupported precision or block size";
     case MGS_ERR_WORKSPACE: return "workspace too small";
     case MGS_ERR_LAUNCH: return "kernel launch failed";
-    case MGS_ERR_UNSUPPORTED: return "unsupported operation";
+    case MGS_ERR_UNSUPPORTED: return "unsupported operation or schedule";
   }
   return "unknown status";
 }
@@ -572,10 +572,11 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes) {
   return MGS_ERR_UNSUPPORTED;
 }
 
-int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq, double *R, int ldr,
-           const double *b, double *y, double *rho, void *work, size_t work_bytes, int *info,
-           mgs_stream_t stream) {
+int mgs_qr_schedule(int m, int n, int prec, const double *A, int lda, double *Q, int ldq, double *R, int ldr,
+                    const double *b, double *y, double *rho, void *work, size_t work_bytes, int *info,
+                    int schedule, mgs_stream_t stream) {
   if (prec != 2 && prec != 4) return MGS_ERR_PREC;
+  if (schedule < MGS_SCHED_AUTO || schedule > MGS_SCHED_SMALL) return MGS_ERR_UNSUPPORTED;
   if (n < 1 || m < n || m > max_rows(prec) || lda < m || ldq < m || ldr < n) return MGS_ERR_DIMS;
   if (!aligned8(A) || !aligned8(Q) || !aligned8(R) || !aligned8(info)) return MGS_ERR_POINTER;
   if (Q == A && ldq != lda) return MGS_ERR_POINTER;
@@ -606,21 +607,28 @@ int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq,
   a.kbase = 0;
   a.init_info = 1;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int mode = schedule_mode();
-  if (mode == 0 || mode == 3) {
+  const int mode = schedule;
+  if (mode == MGS_SCHED_AUTO || mode == MGS_SCHED_SMALL) {
     const int rc = prec == 2 ? small_launch_dd(a, st) : 1;
     if (rc != 1) return rc;
-    if (mode == 3) return MGS_ERR_DIMS;
+    if (mode == MGS_SCHED_SMALL) return MGS_ERR_DIMS;
   }
-  if (mode == 0 || mode == 2) {
+  if (mode == MGS_SCHED_AUTO || mode == MGS_SCHED_RESIDENT) {
     void *sync = static_cast<char *>(work) + qr_w_bytes(m, prec);
     double *u = reinterpret_cast<double *>(static_cast<char *>(sync) + sizeof(unsigned int) * RES_SYNC_WORDS);
     const int rc = prec == 2 && qr_u_bytes(m, n, prec) > 0 ? res_launch_dd(a, sync, u, st) : 1;
     if (rc != 1) return rc;
-    if (mode == 2) return MGS_ERR_DIMS;
+    if (mode == MGS_SCHED_RESIDENT) return MGS_ERR_DIMS;
   }
   if (prec == 2) return dispatch_shape<PrecDD>(a, sh, st);
   return dispatch_shape<PrecQD>(a, sh, st);
+}
+
+int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq, double *R, int ldr,
+           const double *b, double *y, double *rho, void *work, size_t work_bytes, int *info,
+           mgs_stream_t stream) {
+  return mgs_qr_schedule(m, n, prec, A, lda, Q, ldq, R, ldr, b, y, rho, work, work_bytes, info, MGS_SCHED_AUTO,
+                         stream);
 }
 
 int ls_backsolve(int n, int prec, const double *R, int ldr, const double *y, double *x, int *info,
@@ -670,7 +678,7 @@ int mgs_refine_solve(int m, int n, int prec, const double *A, int lda, const dou
                      mgs_stream_t stream) {
   if (prec != 2 && prec != 4) return MGS_ERR_PREC;
   if (n < 1 || m < n || m > max_rows(prec) || lda < m || max_iter < 0) return MGS_ERR_DIMS;
-  if (block != NBP) return MGS_ERR_UNSUPPORTED;
+  if (block != NBP) return MGS_ERR_PREC;
   if (!aligned8(A) || !aligned8(b) || !aligned8(x) || !aligned8(work) || !aligned8(info)) return MGS_ERR_POINTER;
   if (x == b || x == A) return MGS_ERR_POINTER;
   if (work_bytes < refine_layout(m, n, prec, nullptr).bytes) return MGS_ERR_WORKSPACE;

@@ -67,7 +67,27 @@ struct ResArgs {
   int xcd_group;        // logical workgroups per XCD (G / 8), 0 for identity numbering
   int defer;            // look-ahead window of the critical-path-first rule (columns, >= 1)
   long long spin_ticks;  // wall-clock limit of one wait
+#ifdef MGS_TRACE
+  long long *trace;  // diagnostic builds only: RES_TRACE_SLOTS wall-clock stamps per column
+#endif
 };
+
+// Diagnostic builds (-DMGS_TRACE) stamp the wall clock at the steps of the
+// critical chain, per column: 0 poll of the hand-off started, 1 hand-off
+// data arrived, 2 last projection applied, 3 column handed on (stores
+// issued), 4 column normalised and published.
+constexpr int RES_TRACE_SLOTS = 8;
+#ifdef MGS_TRACE
+#define RES_TRACE(col, slot)                                                                   \
+  do {                                                                                         \
+    if (a.trace != nullptr && threadIdx.x == 0)                                                \
+      a.trace[(size_t)(col) * RES_TRACE_SLOTS + (slot)] = (long long)wall_clock64();           \
+  } while (0)
+#else
+#define RES_TRACE(col, slot) \
+  do {                       \
+  } while (0)
+#endif
 
 // Sentinel column index of an empty slot.
 constexpr int RES_NONE = 1 << 30;
@@ -83,6 +103,11 @@ constexpr int RES_ABORT = RES_SYNC_WORDS - 1;
 // signalling NaN, which no arithmetic produces, so a reader knows an entry
 // of q_k has arrived when it differs from it.
 constexpr long long RES_EMPTY = 0x7ff4a5a5a5a5a5a5LL;
+
+// v, or a quiet NaN when v carries the empty marker's bit pattern.
+__device__ __forceinline__ double res_unmark(double v) {
+  return __double_as_longlong(v) == RES_EMPTY ? __longlong_as_double(0x7ff8000000000000LL) : v;
+}
 
 // Widest panel the resident schedule factors.
 constexpr int RES_BWMAX = 4;
@@ -330,9 +355,14 @@ struct Resident {
   }
 
   // This thread's rows of the owned column x, with device-scope stores,
-  // into U (the hand-off to the next two columns' owners).
+  // into U (the hand-off to the owners of the next `defer` columns).
+  // Column 0 receives no projection, so its entries are the raw input: an
+  // entry with the bit pattern of the empty marker is stored as a quiet
+  // NaN instead (every other column has passed through arithmetic, which
+  // never yields a signalling NaN), so that readers never wait on it.
   __device__ __forceinline__ void store_u(int x) {
     double *dst = a.U + (size_t)x * a.ldu;
+    const bool raw = x == 0;
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
       constexpr int s = decltype(sI)::value;
       if (cidx[s] == x) {
@@ -340,10 +370,17 @@ struct Resident {
         for (int r = 0; r < RR; ++r) {
           const int i = row_of(r, RWG);
           if (i < a.m) {
-            coh_store(dst + i, col[s][r].re.h);
-            coh_store(dst + i + a.planeU, col[s][r].im.h);
-            coh_store(dst + i + 2 * a.planeU, col[s][r].re.l);
-            coh_store(dst + i + 3 * a.planeU, col[s][r].im.l);
+            C v = col[s][r];
+            if (raw) {
+              v.re.h = res_unmark(v.re.h);
+              v.im.h = res_unmark(v.im.h);
+              v.re.l = res_unmark(v.re.l);
+              v.im.l = res_unmark(v.im.l);
+            }
+            coh_store(dst + i, v.re.h);
+            coh_store(dst + i + a.planeU, v.im.h);
+            coh_store(dst + i + 2 * a.planeU, v.re.l);
+            coh_store(dst + i + 3 * a.planeU, v.im.l);
           }
         }
       }
@@ -445,7 +482,11 @@ struct Resident {
         for (int r = 0; r < RR; ++r) P::upd(col[s][r], rk, u[r]);
       }
     });
-    if (last) store_u(ps);
+    if (last) {
+      RES_TRACE(ps, 2);
+      store_u(ps);
+      RES_TRACE(ps, 3);
+    }
   }
 
   __device__ __forceinline__ void copy_own(int k, C (&q)[RR]) {
@@ -643,7 +684,9 @@ struct Resident {
       } else if (qsrc == 2) {
         if (!load_col(a.Q, a.ldq, a.planeQ, opk, q)) return;  // already published
       } else if (qsrc == 4) {
+        if (opk + 1 == ps) RES_TRACE(ps, 0);
         if (!load_col(a.U, a.ldu, a.planeU, opk, q)) return;
+        if (opk + 1 == ps) RES_TRACE(ps, 1);
       }
       if (mode == 1) {
         apply(q, opk, lo, RES_NONE);
@@ -654,8 +697,12 @@ struct Resident {
         // U[ps] is due unless the last projection was a look-ahead step
         // (not so for column 0, or when q_{ps-1} is this workgroup's own
         // and reached column ps as a deferred projection).
-        if (handed != ps) store_u(ps);
+        if (handed != ps) {
+          store_u(ps);
+          RES_TRACE(ps, 3);
+        }
         own_norm(ps, q);
+        RES_TRACE(ps, 4);
       }
       qk = opk;
 

@@ -9,11 +9,8 @@ bitwise.
 Both schedules of the factorisation are checked on every random shape: the
 automatic choice (in dd the single cooperative launch whenever the columns
 fit in registers, m <= 1024) and the per-panel launches
-(MGSQR_SCHEDULE=panel).
+(mgs_qr_schedule with the panel schedule).
 """
-import contextlib
-import os
-
 import numpy as np
 import pytest
 
@@ -39,26 +36,9 @@ def N(t):
     return None if t is None else t.cpu().numpy()
 
 
-@contextlib.contextmanager
-def schedule(name):
-    old = os.environ.get("MGSQR_SCHEDULE")
-    if name == "auto":
-        os.environ.pop("MGSQR_SCHEDULE", None)
-    else:
-        os.environ["MGSQR_SCHEDULE"] = name
-    try:
-        yield
-    finally:
-        if old is None:
-            os.environ.pop("MGSQR_SCHEDULE", None)
-        else:
-            os.environ["MGSQR_SCHEDULE"] = old
-
-
 def gpu_lstsq(A, b, sched="auto"):
-    with schedule(sched):
-        f = api.lstsq(T(A), T(b))
-        torch.cuda.synchronize()
+    f = api.lstsq(T(A), T(b), schedule=None if sched == "auto" else sched)
+    torch.cuda.synchronize()
     return {k: N(v) for k, v in f.items()}
 
 
@@ -137,18 +117,17 @@ def test_dd_small_schedule_in_place_and_refusals():
     from paper_1210_0800_amd import _lib
 
     p = inputs.random_problem(2, 40, 30, seed=11, config=55)
-    with schedule("small"):
-        f = api.mgs_qr(T(p["A"]))
-        Q1, R1 = N(f["Q"]), N(f["R"])
-        Ain = T(p["A"])
-        f2 = api.mgs_qr(Ain, Q=Ain)
-        torch.cuda.synchronize()
-        assert np.array_equal(N(Ain), Q1) and np.array_equal(N(f2["R"]), R1)
-        for prec, m, n in ((2, 65, 20), (2, 64, 64), (4, 32, 32)):
-            q = inputs.random_problem(prec, m, n, seed=3, config=55)
-            with pytest.raises(_lib.MgsError) as err:
-                api.mgs_qr(T(q["A"]), T(q["b"]))
-            assert err.value.status == -1
+    f = api.mgs_qr(T(p["A"]), schedule="small")
+    Q1, R1 = N(f["Q"]), N(f["R"])
+    Ain = T(p["A"])
+    f2 = api.mgs_qr(Ain, Q=Ain, schedule="small")
+    torch.cuda.synchronize()
+    assert np.array_equal(N(Ain), Q1) and np.array_equal(N(f2["R"]), R1)
+    for prec, m, n in ((2, 65, 20), (2, 64, 64), (4, 32, 32)):
+        q = inputs.random_problem(prec, m, n, seed=3, config=55)
+        with pytest.raises(_lib.MgsError) as err:
+            api.mgs_qr(T(q["A"]), T(q["b"]), schedule="small")
+        assert err.value.status == -1
 
 
 def test_config1_dd_32x32():
@@ -245,6 +224,22 @@ def test_non_finite_column_reports_first(m, n, sched):
     assert int(g["info"][0]) == 8, sched
 
 
+@pytest.mark.parametrize("m,n,sched", [(48, 30, "small"), (48, 30, "resident"), (48, 30, "panel"),
+                                       (300, 200, "resident"), (300, 200, "panel")])
+def test_marker_bit_pattern_input_reports_info(m, n, sched):
+    """Entries holding the exact bit pattern the single-launch schedule uses
+    to mark not-yet-written data (a signalling NaN) in columns 1 and 6:
+    info names column 1 and the run ends normally on every schedule."""
+    p = inputs.random_problem(2, m, n, seed=9, config=57)
+    A = p["A"].copy()
+    marker = np.array([0x7FF4A5A5A5A5A5A5], dtype=np.uint64).view(np.float64)[0]
+    A[0, 0, 0, 5] = marker
+    A[1, 1, 0, 9] = marker
+    A[0, 1, 5, 2] = marker
+    g = gpu_lstsq(A, p["b"], sched)
+    assert int(g["info"][0]) == 1, sched
+
+
 @pytest.mark.parametrize("sched", ["auto", "panel"])
 def test_reproducible_bitwise(sched):
     p = inputs.random_problem(2, 700, 400, seed=5, config=56)
@@ -277,12 +272,11 @@ def test_resident_schedule_applies_where_documented():
 
     for prec, m, n, ok in ((2, 1024, 1024, True), (2, 300, 200, True), (2, 1100, 40, False), (4, 300, 200, False)):
         p = inputs.random_problem(prec, m, n, seed=m + n, config=58)
-        with schedule("resident"):
-            if ok:
-                f = api.mgs_qr(T(p["A"]), T(p["b"]))
-                torch.cuda.synchronize()
-                assert int(f["info"].item()) == 0
-            else:
-                with pytest.raises(_lib.MgsError) as e:
-                    api.mgs_qr(T(p["A"]), T(p["b"]))
-                assert e.value.status == -1
+        if ok:
+            f = api.mgs_qr(T(p["A"]), T(p["b"]), schedule="resident")
+            torch.cuda.synchronize()
+            assert int(f["info"].item()) == 0
+        else:
+            with pytest.raises(_lib.MgsError) as e:
+                api.mgs_qr(T(p["A"]), T(p["b"]), schedule="resident")
+            assert e.value.status == -1

@@ -78,6 +78,77 @@ def test_exact_invariants(L, m, n):
         assert math.hypot(float(d[0]), float(d[1])) <= 20 * kap * m * n * eps * vnorm(bc)
 
 
+# ------------------------------------------- the error measures themselves --
+def _exact_measures(A, Q, R):
+    """(e_max of Equation (2), max_j ||a_j - Q r_j|| / ||a_j||, max |Q^H Q - I|)
+    from exact rational arithmetic on the limbs, rounded at the end."""
+    Ac, Qc, Rc = cmat(A), cmat(Q), cmat(R)
+    n, m = len(Ac), len(Ac[0])
+    emax = bw = orth = 0.0
+    for j in range(n):
+        res = list(Ac[j])
+        for l in range(j + 1):
+            res = [csub(res[i], cmul(Qc[l][i], Rc[j][l])) for i in range(m)]
+        emax = max(emax, max(math.hypot(float(v[0]), float(v[1])) for v in res))
+        bw = max(bw, vnorm(res) / vnorm(Ac[j]))
+        for l in range(n):
+            g = inner(Qc[l], Qc[j])
+            if l == j:
+                g = (g[0] - 1, g[1])
+            orth = max(orth, math.hypot(float(g[0]), float(g[1])))
+    return emax, bw, orth
+
+
+def _close(a, b, rel=1e-13):
+    return abs(a - b) <= rel * max(abs(a), abs(b)) or (a == 0.0 and b == 0.0)
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+@pytest.mark.parametrize("m,n", [(4, 3), (7, 7), (9, 5)])
+def test_error_measures_equal_exact_values(L, m, n):
+    """oracle.errors returns what the exact rational computation of the three
+    measures returns (to the FP64 rounding of the final value), on the
+    oracle's own factors and on factors with planted defects: a column of Q
+    scaled by 1 + 2^-30 (non-orthogonal, with a backward error), an entry
+    of R with its imaginary sign flipped, and Q with a column leaking into
+    another.  A dropped -1 on the diagonal, a wrong sign in the imaginary
+    cross term or a norm over the wrong range changes these values."""
+    p = inputs.random_problem(L, m, n, seed=m * 3 + n, config=94)
+    A = p["A"]
+    o = oracle.mgs(A)
+    cases = [("factors", o["Q"], o["R"])]
+    Q1 = o["Q"].copy()
+    Q1[:, :, 1] *= 1.0 + 2.0 ** -30
+    cases.append(("scaled q", Q1, o["R"]))
+    R2 = o["R"].copy()
+    R2[:, 1, n - 1, 0] *= -1.0
+    cases.append(("conjugated r", o["Q"], R2))
+    Q3 = o["Q"].copy()
+    Q3[0, :, n - 1] += 2.0 ** -20 * o["Q"][0, :, 0]
+    cases.append(("leaking q", Q3, o["R"]))
+    for name, Qx, Rx in cases:
+        got = oracle.errors(A, Qx, Rx)
+        exact = _exact_measures(A, Qx, Rx)
+        for k in range(3):
+            assert _close(got[k], exact[k]), (name, k, got, exact)
+    # the planted defects are reported at their size
+    assert oracle.errors(A, Q1, o["R"])[2] >= 2.0 ** -30
+    assert oracle.errors(A, Q3, o["R"])[2] >= 2.0 ** -21
+
+
+def test_error_measures_zero_for_exact_factors():
+    """Dyadic unitary Q and its exact R: all three measures are exactly 0."""
+    v = np.array([1 + 1j, 1 + 1j, 1 - 1j, 1j, 1, 0, 0, 0])
+    H = np.eye(8) - 2 * np.outer(v, v.conj()) / 8
+    n = 5
+    A = np.zeros((2, 2, n, 8))
+    A[0, 0] = H[:, :n].real.T
+    A[0, 1] = H[:, :n].imag.T
+    R = np.zeros((2, 2, n, n))
+    R[0, 0] = np.eye(n)
+    assert list(oracle.errors(A, A, R)) == [0.0, 0.0, 0.0]
+
+
 # ------------------------------------------------------ Cayley exact QR -----
 def _cayley(n, rng):
     """Exact orthogonal Q0 = (I - S)(I + S)^-1 for a small-integer skew S, and det(I+S)."""
