@@ -10,8 +10,9 @@ Prints one JSON line: solves/s, the roofline of the dominant kernel sequence
 (the MGS factorisation, FP64 vector ALU bound), the CPU oracle baseline and
 the precision form measured against plain MGS at equal error on the
 2048 x 2048, kappa = 1e10 workload (time, error against x_true, iterations,
-in dd and qd), and small square solves beside the paper's Tesla C2050
-figures (context only).
+in dd and qd), small square solves beside the paper's Tesla C2050
+figures (context only), and batches of 10,000 independent 32 x 32 systems
+in one call (double, dd, qd).
 
 --copy-probe BYTES only copies a device buffer of that size (for scaling the
 HBM counters of a profiler run) and exits.
@@ -302,6 +303,41 @@ def workloads(torch, api):
     return out
 
 
+def batched(torch, api, count=10000, reps=5):
+    """Many independent systems in one call (mgs_lstsq_batched, one
+    workgroup per system): `count` dd systems of configuration 1 (32 x 32),
+    and as many random 32 x 32 systems in complex double and qd."""
+    from paper_1210_0800_amd import inputs
+
+    dev = torch.device("cuda:0")
+    out = {"protocol": "one mgs_lstsq_batched call of %d systems (MGS on [A b] + back substitution each), "
+                       "mean of %d calls after one warm-up" % (count, reps)}
+    t = time.perf_counter()
+    d1 = inputs.config1_batch(count, workers=min(16, len(os.sched_getaffinity(0))))
+    gen = time.perf_counter() - t
+    cases = [("dd_32x32_config1", d1["A"], d1["b"], 2)]
+    for prec, name in ((1, "d_32x32"), (4, "qd_32x32")):
+        g = inputs.rng(81, prec, 0)
+        A = np.stack([inputs.random_complex(g, (32, 32), prec) for _ in range(count)])
+        b = np.stack([inputs.random_complex(g, (32,), prec) for _ in range(count)])
+        cases.append((name, A, b, prec))
+    for name, A, b, prec in cases:
+        At, bt = torch.from_numpy(np.ascontiguousarray(A)).to(dev), torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+        f = api.lstsq_batched(At, bt)
+        torch.cuda.synchronize()
+        bad = int((f["info"] != 0).sum().item())
+
+        def one():
+            api.lstsq_batched(At, bt, Q=f["Q"], R=f["R"], x=f["x"], info=f["info"])
+
+        rate = _rate(torch, one, reps, warm=1) * count
+        out[name] = {"systems_per_s": rate, "failed_systems": bad, "systems": count}
+        print("bench: batched %s: %.0f systems/s (%d systems per call)" % (name, rate, count),
+              file=sys.stderr, flush=True)
+    out["inputs_s"] = gen
+    return out
+
+
 def copy_probe(nbytes):
     import torch
 
@@ -324,6 +360,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--only-precision-form", action="store_true")
     ap.add_argument("--only-context", action="store_true")
+    ap.add_argument("--only-batched", action="store_true")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -335,6 +372,13 @@ def main():
 
         print(json.dumps({"paper_context": paper_context(torch, api), "workloads": workloads(torch, api)}),
               flush=True)
+        return
+    if args.only_batched:
+        import torch
+
+        from paper_1210_0800_amd import api
+
+        print(json.dumps({"batched": batched(torch, api)}), flush=True)
         return
     if args.only_precision_form:
         import torch
@@ -441,6 +485,7 @@ def main():
         out["precision_form"] = precision_form(torch, api)
         out["paper_context"] = paper_context(torch, api)
         out["workloads"] = workloads(torch, api)
+        out["batched"] = batched(torch, api)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host[:4])
     print(json.dumps(out), flush=True)

@@ -11,7 +11,9 @@
  *
  * ------------------------------------------------------------------------
  * Number formats and layout ("planar", all device memory, float64):
- *   prec = number of FP64 limbs per real number: 2 (dd) or 4 (qd).
+ *   prec = number of FP64 limbs per real number: 1 (complex double, the
+ *   paper's third precision), 2 (dd) or 4 (qd).  Entry points say which
+ *   they accept.
  *   A complex matrix with `cols` columns, leading dimension ld >= rows, is
  *   2*prec planes of ld*cols doubles each; plane p = 2*limb + part holds
  *   limb `limb` of the real (part 0) or imaginary (part 1) parts,
@@ -66,16 +68,16 @@ enum {
 
 enum { MGS_OP_QR = 0, MGS_OP_SOLVE = 1, MGS_OP_ADJOINT = 2, MGS_OP_REFINE = 3, MGS_OP_QR64 = 4 };
 
-/* Largest supported row count m: dd 4096, qd 2048. */
+/* Largest supported row count m: double and dd 4096, qd 2048. */
 #define MGS_MAX_ROWS_DD 4096
 #define MGS_MAX_ROWS_QD 2048
 
 int mgs_abi_version(void);
 const char *mgs_status_string(int status);
 
-/* Bytes of device workspace needed by operation `op` (MGS_OP_QR,
- * MGS_OP_SOLVE, MGS_OP_ADJOINT, MGS_OP_REFINE with prec 2 or 4;
- * MGS_OP_QR64 with prec 1) for an m x n problem;
+/* Bytes of device workspace needed by operation `op` (MGS_OP_QR and
+ * MGS_OP_SOLVE with prec 1, 2 or 4; MGS_OP_ADJOINT and MGS_OP_REFINE with
+ * prec 2 or 4; MGS_OP_QR64 with prec 1) for an m x n problem;
  * written to *bytes.  A workspace may be reused by later calls on the same
  * stream; calls that may overlap need distinct workspaces. */
 int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
@@ -100,9 +102,11 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
  *             in dd with m <= 1024, its hand-off copy of the columns,
  *             32 m n bytes).
  *   info      device int, see above.
- * Requires 1 <= n <= m <= MGS_MAX_ROWS_{DD,QD}.
- * Schedule: in dd with m <= 64 and at most 64 columns of [A b], one
- * workgroup (a column per wave slot, q vectors through LDS); in dd when
+ * prec 1, 2 or 4.  Requires 1 <= n <= m <= MGS_MAX_ROWS_{DD,QD}.
+ * Schedule: with m <= 64 and at most 64 columns of [A b] (and, in qd, the
+ * q vectors within 159 KiB: 64 m n bytes), one workgroup (a column per wave
+ * slot, q vectors through LDS; for double and qd the kernel of
+ * mgs_lstsq_batched on one system); in dd when
  * every column fits in the register file of the device (m <= 1024 and at
  * most 5 columns per compute unit, 8 when m <= 512, e.g. 1024 x 1024 with b
  * on 256 compute units) one cooperative launch with the columns held in
@@ -140,7 +144,8 @@ int mgs_qr_schedule(int m, int n, int prec, const double *A, int lda, double *Q,
  * the augmented column of Equation (1)), then the back substitution of
  * Section 6, Figure 3.
  *   Q  [in] m x n planar (ldq), R [in] n x n planar (ldr), b [in] m planar,
- *   x  [out] n planar.  work: mgs_workspace_size(m, n, prec, MGS_OP_SOLVE).
+ *   x  [out] n planar.  prec 1, 2 or 4.
+ *   work: mgs_workspace_size(m, n, prec, MGS_OP_SOLVE).
  */
 int ls_solve(int m, int n, int prec, const double *Q, int ldq, const double *R, int ldr,
              const double *b, double *x, void *work, size_t work_bytes, int *info,
@@ -153,7 +158,7 @@ int ls_solve(int m, int n, int prec, const double *Q, int ldq, const double *R, 
  *   R [in] n x n planar (ldr >= n), upper triangle and real diagonal read;
  *   y [in] n planar (not modified); x [out] n planar.
  *   info: 0, or k > 0 when r_kk is zero or not finite (smallest such k).
- * Requires 1 <= n <= MGS_MAX_ROWS_{DD,QD}.
+ * prec 1, 2 or 4.  Requires 1 <= n <= MGS_MAX_ROWS_{DD,QD}.
  */
 int ls_backsolve(int n, int prec, const double *R, int ldr, const double *y, double *x, int *info,
                  mgs_stream_t stream);
@@ -230,6 +235,39 @@ int mgs_refine_solve(int m, int n, int prec, const double *A, int lda, const dou
  */
 int mgs_qr64(int m, int n, const double *A, int lda, const double *b, double *Q, int ldq, double *R, int ldr,
              double *y, int block, void *work, size_t work_bytes, int *info, mgs_stream_t stream);
+
+/*
+ * mgs_lstsq_batched -- `batch` independent systems, each factored by the MGS
+ * of Figure 1 (Section 3) on [A_s b_s] (Equation (1)) and, when b is given,
+ * solved by the back substitution of Section 6, Figure 3: the many small
+ * systems of many paths (Section 2), all resident on the card (Section 7).
+ * One workgroup per system; systems are independent, so their order of
+ * completion is unspecified and each system's results are the same as for a
+ * batch of one.
+ *   prec 1, 2 or 4.  Requires 1 <= n <= m <= 64, at most 64 columns of
+ *   [A b], and 16 prec m n <= 162816 (the q vectors of a system in LDS;
+ *   binding for qd only: e.g. m = n = 50).  batch >= 0 (0: nothing to do,
+ *   pointers not examined).
+ *   A  [in]  batch systems back to back: system s at A + s*2*prec*lda*n,
+ *            each m x n planar with leading dimension lda >= m (a torch view
+ *            [batch, prec, 2, n, lda]).
+ *   b  [in]  batch vectors of m (system s at b + s*2*prec*m) or NULL (QR only).
+ *   Q  [out] like A with ldq >= m; Q == A (ldq == lda) overwrites A.
+ *   R  [out] batch n x n planar (ldr >= n), system s at R + s*2*prec*ldr*n:
+ *            upper triangular, real positive diagonal, lower triangle 0.
+ *   y  [out] batch vectors of n (system s at y + s*2*prec*n) or NULL: the
+ *            projections Q^H b.
+ *   x  [out] batch vectors of n or NULL: the least-squares solutions.
+ *            With b given, at least one of y and x is required; x != y.
+ *   rho[out] batch x prec doubles or NULL: ||b_s - A_s x_s|| (Equation (1)).
+ *   info [out] batch device ints: 0, k > 0 when column k of that system had
+ *            a zero or non-finite norm (its x is then not computed and its
+ *            later columns are unspecified), or MGS_INFO_SYNC_TIMEOUT.
+ * No workspace.
+ */
+int mgs_lstsq_batched(int batch, int m, int n, int prec, const double *A, int lda, const double *b, double *Q,
+                      int ldq, double *R, int ldr, double *y, double *x, double *rho, int *info,
+                      mgs_stream_t stream);
 
 #ifdef __cplusplus
 }

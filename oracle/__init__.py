@@ -13,7 +13,9 @@ and quad-double arithmetic, of what the paper defines:
 * least squares by sequential projections of b followed by back substitution,
 * the accuracy measure e of Section 4, Equation (2),
 * the closed-form adjoint (dL/dA, dL/db) of the least-squares solution for
-  L = Re(g^H x) (the differentiation form; not in the paper).
+  L = Re(g^H x) (the differentiation form; not in the paper),
+* the precision form (not in the paper): FP64 blocked MGS, then iterative
+  refinement with the residual in quad-double.
 
 Array layout ("planar"): a complex matrix with ``cols`` columns and leading
 dimension ``ld`` in L-limb precision is a float64 array of shape
@@ -28,22 +30,29 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liborc_mgs.so")
+# ORC_MGS_LIB names another build of the same source (the sanitizer build
+# of the tests); the default is the in-tree library.
+_SO = os.environ.get("ORC_MGS_LIB") or os.path.join(_HERE, "liborc_mgs.so")
 _SRC = [os.path.join(_HERE, "orc_mgs.cpp"), os.path.join(_HERE, "orc_arith.hpp")]
 
 CXXFLAGS = ["-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-march=x86-64-v3",
             "-fopenmp", "-fPIC", "-shared", "-Wall"]
 
 
-def build(force=True):
-    """Compile the oracle library in place with g++."""
-    if not force and os.path.exists(_SO):
-        return _SO
-    tmp = _SO + ".tmp%d" % os.getpid()
-    cmd = ["g++"] + CXXFLAGS + ["-o", tmp, _SRC[0]]
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(force=True, out=None, sanitize=False):
+    """Compile the oracle library with g++ (in place unless ``out`` names
+    another file; ``sanitize`` adds AddressSanitizer and UBSan)."""
+    so = out or _SO
+    if not force and os.path.exists(so):
+        return so
+    tmp = so + ".tmp%d" % os.getpid()
+    cmd = ["g++"] + CXXFLAGS + (SANITIZE if sanitize else []) + ["-o", tmp, _SRC[0]]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _SO)
-    return _SO
+    os.replace(tmp, so)
+    return so
 
 
 _lib = None
@@ -63,7 +72,10 @@ def lib():
         L.orc_arith.argtypes = [I, I, I, P, P, P]
         L.orc_errors.argtypes = [I, I, I, P, I, P, I, P, I, P, I, P, I]
         L.orc_adjoint.argtypes = [I, I, I, P, I, P, P, P, P, P, I]
-        for f in (L.orc_mgs, L.orc_backsolve, L.orc_ls_solve, L.orc_arith, L.orc_errors, L.orc_adjoint):
+        L.orc_emax_batch.argtypes = [I, I, I, I, P, I, P, I, P, I, P, I]
+        L.orc_refine.argtypes = [I, I, I, P, I, P, P, P, I, ctypes.c_double, I, P, P, I]
+        for f in (L.orc_mgs, L.orc_backsolve, L.orc_ls_solve, L.orc_arith, L.orc_errors, L.orc_adjoint,
+                  L.orc_emax_batch, L.orc_refine):
             f.restype = I
         _lib = L
     return _lib
@@ -153,6 +165,42 @@ def errors(A, Q, R, cols=None, nthreads=0):
     lib().orc_errors(L, m, n, _p(A), m, _p(Q), m, _p(R), n, _p(cj), 0 if cj is None else len(cj),
                      _p(out), int(nthreads))
     return out
+
+
+def emax_batch(A, Q, R, nthreads=0):
+    """e_max of Equation (2) for each system of a batch: A, Q (count,L,2,n,m),
+    R (count,L,2,n,n); evaluated exactly as by ``errors``, one system per
+    thread.  Returns a float64 array of count values."""
+    A, Q, R = _c(A), _c(Q), _c(R)
+    count, L, _, n, m = A.shape
+    out = np.zeros(count)
+    rc = lib().orc_emax_batch(L, count, m, n, _p(A), m, _p(Q), m, _p(R), n, _p(out), int(nthreads))
+    if rc != 0:
+        raise ValueError("orc_emax_batch error %d" % rc)
+    return out
+
+
+def refine(A, b, block=64, tol=None, max_iter=30, nthreads=0):
+    """The precision form: FP64 blocked MGS of [fl64(A) fl64(b)] (panels of
+    ``block``), x0 = R^-1 y, then refinement with the residual in qd and the
+    FP64 correction solve replaying the panels' projections.
+
+    Returns dict(x, x0, iters, err_est, info): info 0 converged, -1
+    stagnated, -2 max_iter reached, k > 0 bad column k.
+    """
+    A, b = _c(A), _c(b)
+    L, _, n, m = A.shape
+    if tol is None:
+        tol = 2.0 ** -104 if L == 2 else 2.0 ** -209
+    x = np.zeros((L, 2, n))
+    x0 = np.zeros((L, 2, n))
+    it = ctypes.c_int(0)
+    est = ctypes.c_double(0.0)
+    info = lib().orc_refine(L, m, n, _p(A), m, _p(b), _p(x), _p(x0), int(block), float(tol), int(max_iter),
+                            ctypes.byref(it), ctypes.byref(est), int(nthreads))
+    if info < -2:
+        raise ValueError("orc_refine argument error %d" % info)
+    return dict(x=x, x0=x0, iters=it.value, err_est=est.value, info=info)
 
 
 def adjoint(A, b, g, nthreads=0):

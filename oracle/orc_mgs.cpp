@@ -265,9 +265,10 @@ static inline double exp_value(const double *e, int n) {
 //   out[1] = max_j ||a_j - Q r_j||_2 / ||a_j||_2,
 //   out[2] = max_lj |(Q^H Q - I)_lj|.
 // Columns j are those listed in `cols` (all when cols == NULL).
+// With orth == false only out[0] and out[1] are formed (out[2] = 0).
 template <class T>
 void run_errors(int m, int n, const double *A, int lda, const double *Q, int ldq, const double *R,
-                int ldr, const int *cols, int ncols, double *out, int nthreads) {
+                int ldr, const int *cols, int ncols, double *out, int nthreads, bool orth_too = true) {
   const int L = Limbs<T>::L;
   CV<T> Av, Qv, Rv;
   read_planar<T>(A, m, n, lda, Av);
@@ -309,7 +310,7 @@ void run_errors(int m, int n, const double *A, int lda, const double *Q, int ldq
     emax[t] = e;
     bw[t] = (a2 > 0) ? std::sqrt(s2 / a2) : 0.0;
     double o = 0.0;
-    for (int l = 0; l < n; ++l) {
+    for (int l = 0; orth_too && l < n; ++l) {
       int nr = 0, ni = 0;
       if (l == j) { double one = 1.0; nr = exp_add_limbs(er.data(), 0, &one, 1, -1.0); }
       for (int i = 0; i < m; ++i) {
@@ -337,6 +338,126 @@ void run_errors(int m, int n, const double *A, int lda, const double *Q, int ldq
 }
 
 int threads_or_default(int t) { return t > 0 ? t : omp_get_max_threads(); }
+
+// ------------------------------------------------------ precision form ----
+// Not in the paper: the refinement built around its solver.  Written from
+// its definition:
+//   1. [fl64(A) fl64(b)] is factored in FP64 by blocked MGS with panels of
+//      `block` columns: inside a panel, MGS as in Figure 1; every later
+//      column a_j (b included) then takes the panel's inner products
+//      w_kj = q_k^H a_j, all from the same a_j, and a_j -= q_k w_kj for k
+//      ascending.  y = the projections of b; x0 = R^{-1} y (Figure 3).
+//   2. Repeat: r = b - A x with A, b, x widened exactly to qd and every
+//      operation in qd; d = the FP64 solve of fl64(r): the panels'
+//      projections replayed on r (per panel w = Q_p^H r, all from the same
+//      r, then r -= q_k w_k for k ascending), then R^{-1} w; x += d.
+//      Stop when ||d|| <= tol ||x|| (converged); when ||d|| > ||d_prev|| / 2
+//      (stalled: that d is not applied; converged if the last applied
+//      ||d|| / ||x|| <= sqrt(tol), stagnated otherwise); or after max_iter
+//      steps.  Norms are FP64 2-norms of d and of the leading limbs of x.
+static inline QD widen(double a) { return qd_make(a); }
+static inline QD widen(const DD &a) {
+  QD r;
+  r.x[0] = a.x[0];
+  r.x[1] = a.x[1];
+  r.x[2] = r.x[3] = 0.0;
+  return r;
+}
+static inline QD widen(const QD &a) { return a; }
+template <class T> static inline C<QD> cwiden(const C<T> &a) { return {widen(a.re), widen(a.im)}; }
+
+template <class T>
+int run_refine(int m, int n, const double *A, int lda, const double *b, double *x_out, double *x0_out, int block,
+               double tol, int max_iter, int *iters, double *err_est, int nthreads) {
+  using D = double;
+  CV<T> Av, bv;
+  read_planar<T>(A, m, n, lda, Av);
+  read_planar<T>(b, m, 1, m, bv);
+  // 1. FP64 blocked MGS of [fl64(A) fl64(b)].
+  CV<D> W((size_t)m * (n + 1));
+  for (size_t e = 0; e < (size_t)m * n; ++e) W[e] = {hi(Av[e].re), hi(Av[e].im)};
+  for (int i = 0; i < m; ++i) W[(size_t)n * m + i] = {hi(bv[i].re), hi(bv[i].im)};
+  CV<D> R((size_t)n * (n + 1), czero<D>());  // R[j * n + k]: row k of column j
+  for (int k0 = 0; k0 < n; k0 += block) {
+    const int k1 = k0 + block < n ? k0 + block : n;
+    for (int k = k0; k < k1; ++k) {
+      C<D> *ak = &W[(size_t)k * m];
+      D s = 0.0;
+      for (int i = 0; i < m; ++i) s = add(s, cabs2(ak[i]));
+      if (is_zero(s) || !is_finite(s)) return k + 1;
+      const D rkk = sqrt_(s);
+      for (int i = 0; i < m; ++i) ak[i] = cdivr(ak[i], rkk);
+      R[(size_t)k * n + k] = {rkk, 0.0};
+      for (int j = k + 1; j < k1; ++j) {
+        C<D> *aj = &W[(size_t)j * m];
+        const C<D> r = inner(ak, aj, m);
+        R[(size_t)j * n + k] = r;
+        for (int i = 0; i < m; ++i) aj[i] = csub(aj[i], cmul(r, ak[i]));
+      }
+    }
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+    for (int j = k1; j <= n; ++j) {
+      C<D> *aj = &W[(size_t)j * m];
+      for (int k = k0; k < k1; ++k) R[(size_t)j * n + k] = inner(&W[(size_t)k * m], aj, m);
+      for (int k = k0; k < k1; ++k) {
+        const C<D> *qk = &W[(size_t)k * m];
+        const C<D> w = R[(size_t)j * n + k];
+        for (int i = 0; i < m; ++i) aj[i] = csub(aj[i], cmul(w, qk[i]));
+      }
+    }
+  }
+  CV<D> y(R.begin() + (size_t)n * n, R.begin() + (size_t)n * n + n);
+  CV<D> x64(n);
+  backsolve<D>(n, R.data(), n, y, x64.data());
+  CV<T> x(n);
+  for (int j = 0; j < n; ++j) x[j] = {Limbs<T>::from(x64[j].re), Limbs<T>::from(x64[j].im)};
+  if (x0_out) write_planar<T>(x0_out, n, 1, n, x);
+  // 2. Refinement.
+  int status = 0;  // 0 running, 1 converged, 2 stagnated
+  int it_done = 0;
+  double dprev = INFINITY, est = INFINITY;
+  CV<D> r64(m), wv(n), d(n);
+  for (int it = 1; it <= max_iter && status == 0; ++it) {
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+    for (int i = 0; i < m; ++i) {
+      C<QD> ri = cwiden(bv[i]);
+      for (int j = 0; j < n; ++j) ri = csub(ri, cmul(cwiden(Av[(size_t)j * m + i]), cwiden(x[j])));
+      r64[i] = {hi(ri.re), hi(ri.im)};
+    }
+    for (int k0 = 0; k0 < n; k0 += block) {
+      const int k1 = k0 + block < n ? k0 + block : n;
+      for (int k = k0; k < k1; ++k) wv[k] = inner(&W[(size_t)k * m], r64.data(), m);
+      for (int k = k0; k < k1; ++k) {
+        const C<D> *qk = &W[(size_t)k * m];
+        for (int i = 0; i < m; ++i) r64[i] = csub(r64[i], cmul(wv[k], qk[i]));
+      }
+    }
+    backsolve<D>(n, R.data(), n, wv, d.data());
+    double dn = 0.0, xn = 0.0;
+    for (int j = 0; j < n; ++j) {
+      dn += d[j].re * d[j].re + d[j].im * d[j].im;
+      xn += hi(x[j].re) * hi(x[j].re) + hi(x[j].im) * hi(x[j].im);
+    }
+    dn = std::sqrt(dn);
+    xn = std::sqrt(xn);
+    if (it > 1 && dn > 0.5 * dprev) {
+      status = est <= std::sqrt(tol) ? 1 : 2;
+      break;
+    }
+    for (int j = 0; j < n; ++j) {
+      x[j].re = add(x[j].re, Limbs<T>::from(d[j].re));
+      x[j].im = add(x[j].im, Limbs<T>::from(d[j].im));
+    }
+    it_done = it;
+    est = xn > 0.0 ? dn / xn : dn;
+    dprev = dn;
+    if (dn <= tol * xn) status = 1;
+  }
+  write_planar<T>(x_out, n, 1, n, x);
+  if (iters) *iters = it_done;
+  if (err_est) *err_est = est;
+  return status == 1 ? 0 : (status == 2 ? -1 : -2);
+}
 
 }  // namespace
 
@@ -417,6 +538,45 @@ int orc_errors(int prec, int m, int n, const double *A, int lda, const double *Q
     case 4: run_errors<QD>(m, n, A, lda, Q, ldq, R, ldr, cols, ncols, out, t); return 0;
   }
   return -3;
+}
+
+// The precision form (see run_refine): x (n planar, prec limbs), x0 (the
+// FP64 starting solution widened, or NULL), iters and err_est (or NULL).
+// Returns 0 converged, -1 stagnated, -2 max_iter reached first, k > 0 zero
+// or non-finite norm at column k of the FP64 factorisation, < -2 bad
+// arguments.
+int orc_refine(int prec, int m, int n, const double *A, int lda, const double *b, double *x, double *x0, int block,
+               double tol, int max_iter, int *iters, double *err_est, int nthreads) {
+  if (n < 1 || m < n || lda < m || block < 1 || max_iter < 0) return -11;
+  if (!A || !b || !x) return -12;
+  int t = threads_or_default(nthreads);
+  switch (prec) {
+    case 2: return run_refine<DD>(m, n, A, lda, b, x, x0, block, tol, max_iter, iters, err_est, t);
+    case 4: return run_refine<QD>(m, n, A, lda, b, x, x0, block, tol, max_iter, iters, err_est, t);
+  }
+  return -13;
+}
+
+// e_max of Equation (2) for `count` systems stored back to back (system s
+// at A + s*2*prec*lda*n, Q + s*2*prec*ldq*n, R + s*2*prec*ldr*n): out[s].
+// Threads take whole systems; each system is evaluated as by orc_errors.
+int orc_emax_batch(int prec, int count, int m, int n, const double *A, int lda, const double *Q, int ldq,
+                   const double *R, int ldr, double *out, int nthreads) {
+  if (count < 0 || n < 1 || m < n || lda < m || ldq < m || ldr < n) return -1;
+  if (prec != 1 && prec != 2 && prec != 4) return -3;
+  const size_t sa = (size_t)2 * prec * lda * n, sq = (size_t)2 * prec * ldq * n, sr = (size_t)2 * prec * ldr * n;
+#pragma omp parallel for schedule(dynamic) num_threads(threads_or_default(nthreads))
+  for (int s = 0; s < count; ++s) {
+    double o[3];
+    const double *a = A + s * sa, *q = Q + s * sq, *r = R + s * sr;
+    switch (prec) {
+      case 1: run_errors<double>(m, n, a, lda, q, ldq, r, ldr, nullptr, 0, o, 1, false); break;
+      case 2: run_errors<DD>(m, n, a, lda, q, ldq, r, ldr, nullptr, 0, o, 1, false); break;
+      default: run_errors<QD>(m, n, a, lda, q, ldq, r, ldr, nullptr, 0, o, 1, false); break;
+    }
+    out[s] = o[0];
+  }
+  return 0;
 }
 
 }  // extern "C"

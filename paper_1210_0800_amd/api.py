@@ -2,7 +2,9 @@
 
 Tensors are float64, contiguous, on a HIP device, in the planar layout
 [prec, 2, cols, ld] (matrices) or [prec, 2, len] (vectors): limb, real /
-imaginary part, column, row.  prec = 2 (double-double) or 4 (quad-double).
+imaginary part, column, row.  prec = 1 (complex double), 2 (double-double)
+or 4 (quad-double); the adjoint and the precision form take 2 and 4.
+Batched calls put a leading batch axis in front: [batch, prec, 2, ...].
 Work is enqueued on the current torch stream; nothing is synchronised.
 """
 import torch
@@ -224,6 +226,49 @@ def refine_lstsq(A, b, *, tol=None, max_iter=20, x=None, work=None):
                                      _ptr(info), _stream(A))
     _lib.check("mgs_refine_solve", st)
     return dict(x=x, iters=iters, err_est=err, info=info)
+
+
+def lstsq_batched(A, b=None, *, Q=None, R=None, y=None, x=None, rho=None, info=None, with_y=False,
+                  with_rho=False):
+    """`batch` independent systems: MGS of each [A_s b_s] (Figure 1, Equation
+    (1)) and, when b is given, the back substitution (Figure 3), one
+    workgroup per system (mgs_lstsq_batched).
+
+    A: [batch, prec, 2, n, m], b: [batch, prec, 2, m] or None.  Returns
+    dict(Q, R, y, x, rho, info) (info: one int32 per system); Q may be A
+    itself to factor in place.
+    """
+    if not isinstance(A, torch.Tensor) or A.dim() != 5:
+        raise ValueError("A must be a [batch, prec, 2, n, m] tensor")
+    batch, prec, two, n, m = A.shape
+    dev = A.device
+    if not A.is_contiguous() or A.dtype != torch.float64 or not A.is_cuda or two != 2:
+        raise ValueError("A must be a contiguous float64 [batch, prec, 2, n, m] tensor on a HIP device")
+
+    def out(name, t, shape):
+        t = torch.empty(shape, dtype=torch.float64, device=dev) if t is None else t
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous() or \
+                t.device != dev or tuple(t.shape) != tuple(shape):
+            raise ValueError("%s must be a contiguous float64 tensor of shape %s on %s" % (name, tuple(shape), dev))
+        return t
+
+    Q = out("Q", Q, A.shape)
+    R = out("R", R, (batch, prec, 2, n, n))
+    info = torch.empty(batch, dtype=torch.int32, device=dev) if info is None else info
+    if not isinstance(info, torch.Tensor) or info.dtype != torch.int32 or info.numel() != batch or \
+            info.device != dev or not info.is_contiguous():
+        raise ValueError("info must be a contiguous int32 tensor of %d entries on %s" % (batch, dev))
+    if b is not None:
+        b = out("b", b, (batch, prec, 2, m))
+        x = out("x", x, (batch, prec, 2, n))
+        y = out("y", y, (batch, prec, 2, n)) if (with_y or y is not None) else None
+        rho = out("rho", rho, (batch, prec)) if (with_rho or rho is not None) else None
+    else:
+        x = y = rho = None
+    st = _lib.lib().mgs_lstsq_batched(batch, m, n, prec, _ptr(A), m, _ptr(b), _ptr(Q), m, _ptr(R), n, _ptr(y),
+                                      _ptr(x), _ptr(rho), _ptr(info), _stream(A))
+    _lib.check("mgs_lstsq_batched", st)
+    return dict(Q=Q, R=R, y=y, x=x, rho=rho, info=info)
 
 
 class LstsqFn(torch.autograd.Function):

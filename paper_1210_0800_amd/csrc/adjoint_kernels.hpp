@@ -114,25 +114,54 @@ __global__ __launch_bounds__(BS_T) void fwdsub_blocked_kernel(int n, const doubl
   }
 }
 
-// gb = Q w and r = b - A x, one row per thread, sums over the columns in
-// ascending order in the fused accumulators.
+// gb = Q w and r = b - A x, split over column chunks of ADJ_CH columns so
+// that the grid covers the device (rows x chunks x 2 products): each thread
+// sums one row of one chunk in the fused accumulator (the chunk holding
+// column 0 of r starts from b); adj_finish_kernel merges the chunk partials
+// of a row in chunk order, so results are reproducible.
+constexpr int ADJ_CH = 8;
+constexpr int ADJ_T = 64;
 template <class P>
-__global__ __launch_bounds__(WG) void adj_gemv_kernel(int m, int n, const double *Q, int ldq, size_t planeQ,
-                                                       const double *A, int lda, size_t planeA, const double *b,
-                                                       const double *x, const double *w, double *gb, double *r) {
+__global__ __launch_bounds__(ADJ_T) void adj_partial_kernel(int m, int n, const double *Q, int ldq, size_t planeQ,
+                                                             const double *A, int lda, size_t planeA,
+                                                             const double *b, const double *x, const double *w,
+                                                             typename P::Acc *partial) {
+  using Acc = typename P::Acc;
+  const int i = blockIdx.x * ADJ_T + threadIdx.x;
+  const int cb = blockIdx.y, which = blockIdx.z;  // 0: Q w, 1: b - A x
+  if (i >= m) return;
+  const int nchunk = (n + ADJ_CH - 1) / ADJ_CH;
+  const int j0 = cb * ADJ_CH, j1 = j0 + ADJ_CH < n ? j0 + ADJ_CH : n;
+  Acc acc;
+  if (which == 0) {
+    P::acc_zero(acc);
+#pragma unroll 4
+    for (int k = j0; k < j1; ++k)
+      P::acc_cmul(acc, P::load(Q + (size_t)k * ldq + i, planeQ), P::load(w + k, (size_t)n));
+  } else {
+    if (cb == 0)
+      P::acc_set(acc, P::load(b + i, (size_t)m));
+    else
+      P::acc_zero(acc);
+#pragma unroll 4
+    for (int j = j0; j < j1; ++j)
+      P::acc_cmul(acc, P::load(A + (size_t)j * lda + i, planeA), P::cneg(P::load(x + j, (size_t)n)));
+  }
+  partial[((size_t)which * nchunk + cb) * m + i] = acc;
+}
+
+template <class P>
+__global__ __launch_bounds__(WG) void adj_finish_kernel(int m, int n, const typename P::Acc *partial, double *gb,
+                                                         double *r) {
   using Acc = typename P::Acc;
   const int i = blockIdx.x * WG + threadIdx.x;
+  const int which = blockIdx.y;
   if (i >= m) return;
-  Acc acc;
-  P::acc_zero(acc);
-#pragma unroll 4
-  for (int k = 0; k < n; ++k) P::acc_cmul(acc, P::load(Q + (size_t)k * ldq + i, planeQ), P::load(w + k, (size_t)n));
-  P::store(gb + i, (size_t)m, P::acc_value(acc));
-  P::acc_set(acc, P::load(b + i, (size_t)m));
-#pragma unroll 4
-  for (int j = 0; j < n; ++j)
-    P::acc_cmul(acc, P::load(A + (size_t)j * lda + i, planeA), P::cneg(P::load(x + j, (size_t)n)));
-  P::store(r + i, (size_t)m, P::acc_value(acc));
+  const int nchunk = (n + ADJ_CH - 1) / ADJ_CH;
+  const Acc *p = partial + (size_t)which * nchunk * m + i;
+  Acc acc = p[0];
+  for (int c = 1; c < nchunk; ++c) P::acc_merge(acc, p[(size_t)c * m]);
+  P::store((which == 0 ? gb : r) + i, (size_t)m, P::acc_value(acc));
 }
 
 // gA(i, j) = r_i conj(z_j) - gb_i conj(x_j): two fused updates from zero.

@@ -8,6 +8,8 @@
 #include <cstdint>
 
 #include "adjoint_kernels.hpp"
+#include "backsolve_kernels.hpp"
+#include "batched_kernels.hpp"
 #include "mgs_kernels.hpp"
 #include "precision_kernels.hpp"
 #include "resident_kernels.hpp"
@@ -19,7 +21,8 @@ namespace {
 
 bool aligned8(const void *p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
-int max_rows(int prec) { return prec == 2 ? MGS_MAX_ROWS_DD : MGS_MAX_ROWS_QD; }
+int max_rows(int prec) { return prec == 4 ? MGS_MAX_ROWS_QD : MGS_MAX_ROWS_DD; }
+bool prec_ok(int prec) { return prec == 1 || prec == 2 || prec == 4; }
 int pow2_at_least(int v) {
   int p = 1;
   while (p < v) p <<= 1;
@@ -133,12 +136,49 @@ int dispatch_shape(const StepArgs &a, const Shape &sh, hipStream_t st) {
   return MGS_ERR_DIMS;
 }
 
+struct DevInfo {
+  int cus;  // compute units when cooperative launches are supported, else 0
+  long long wclk_khz;
+};
+bool dev_info(DevInfo &d);
+
+// Back substitution across workgroups (one wave per 64 rows, cooperative);
+// returns 1 when it does not apply (one block only, or the workgroups
+// cannot all be resident), so that the caller takes the one-workgroup
+// kernel.
+template <class P>
+int backsolve_pipe_launch(int n, const double *R, int ldr, size_t planeR, const double *y, size_t planeY, double *x,
+                          int *info, const int *skip, hipStream_t st) {
+  if (n <= BP_ROWS) return 1;
+  DevInfo d;
+  if (!dev_info(d) || d.cus <= 0) return 1;
+  const int G = ceil_div(n, BP_ROWS);
+  auto kern = backsolve_pipe_kernel<P>;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), BP_ROWS, 0) !=
+          hipSuccess ||
+      (long long)per_cu * d.cus < G)
+    return 1;
+  hipLaunchKernelGGL((bs_mark_kernel<P::L>), dim3(ceil_div(n, 256)), dim3(256), 0, st, n, x, info, skip);
+  if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
+  long long spin = d.wclk_khz * 2000;  // 2 s
+  void *args[] = {&n, &R, &ldr, &planeR, &y, &planeY, &x, &info, &skip, &spin};
+  if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G), dim3(BP_ROWS), args, 0, st) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return MGS_OK;
+}
+
 template <class P>
 int backsolve_launch(int n, const double *R, int ldr, const double *y, double *x, int *info, hipStream_t st,
                      size_t planeR = 0, const int *skip = nullptr, size_t planeY = 0) {
   const int ny = pow2_at_least(ceil_div(n, BS_T));
   if (planeR == 0) planeR = (size_t)ldr * n;
   if (planeY == 0) planeY = (size_t)n;
+  const int rc = backsolve_pipe_launch<P>(n, R, ldr, planeR, y, planeY, x, info, skip, st);
+  if (rc != 1) return rc;
 #define MGS_NY_CASE(NYV)                                                                                    \
   case NYV:                                                                                                 \
     hipLaunchKernelGGL((backsolve_blocked_kernel<P, NYV>), dim3(1), dim3(BS_T), 0, st, n, R, ldr, planeR, y, \
@@ -187,9 +227,13 @@ size_t qr_work_bytes(int m, int n, int prec) {
   return qr_w_bytes(m, prec) + sizeof(unsigned int) * RES_SYNC_WORDS + qr_u_bytes(m, n, prec);
 }
 size_t solve_work_bytes(int n, int prec) { return round256(sizeof(double) * 2 * (size_t)prec * n); }
-// adjoint: w (n), z (n), r (m)
+// adjoint: w (n), z (n), r (m), then the chunk partials of Q w and b - A x
+// (2 x chunks x m accumulators).
+size_t adj_acc_bytes(int prec) { return prec == 1 ? sizeof(PrecD::Acc) : prec == 2 ? sizeof(PrecDD::Acc) : sizeof(PrecQD::Acc); }
 size_t adjoint_work_bytes(int m, int n, int prec) {
-  return 2 * round256(sizeof(double) * 2 * (size_t)prec * n) + round256(sizeof(double) * 2 * (size_t)prec * m);
+  const size_t nchunk = (size_t)((n + ADJ_CH - 1) / ADJ_CH);
+  return 2 * round256(sizeof(double) * 2 * (size_t)prec * n) + round256(sizeof(double) * 2 * (size_t)prec * m) +
+         round256(adj_acc_bytes(prec) * 2 * nchunk * m);
 }
 
 template <class P>
@@ -218,12 +262,15 @@ int adjoint_launch(int m, int n, const double *A, int lda, const double *b, cons
   double *w = static_cast<double *>(work);
   double *z = w + round256(sizeof(double) * 2 * P::L * (size_t)n) / sizeof(double);
   double *r = z + round256(sizeof(double) * 2 * P::L * (size_t)n) / sizeof(double);
+  auto *part = reinterpret_cast<typename P::Acc *>(r + round256(sizeof(double) * 2 * P::L * (size_t)m) / sizeof(double));
   int rc = fwdsub_launch<P>(n, R, ldr, gx, w, info, st);
   if (rc != MGS_OK) return rc;
   rc = backsolve_launch<P>(n, R, ldr, w, z, info, st);
   if (rc != MGS_OK) return rc;
-  hipLaunchKernelGGL((adj_gemv_kernel<P>), dim3(ceil_div(m, WG)), dim3(WG), 0, st, m, n, Q, ldq, (size_t)ldq * n,
-                     A, lda, (size_t)lda * n, b, x, w, gb, r);
+  hipLaunchKernelGGL((adj_partial_kernel<P>), dim3(ceil_div(m, ADJ_T), ceil_div(n, ADJ_CH), 2), dim3(ADJ_T), 0, st,
+                     m, n, Q, ldq, (size_t)ldq * n, A, lda, (size_t)lda * n, b, x, w, part);
+  if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
+  hipLaunchKernelGGL((adj_finish_kernel<P>), dim3(ceil_div(m, WG), 2), dim3(WG), 0, st, m, n, part, gb, r);
   if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
   hipLaunchKernelGGL((adj_rank2_kernel<P>), dim3(ceil_div(m, WG), n), dim3(WG), 0, st, m, n, r, z, gb, x, gA, ldga,
                      (size_t)ldga * n);
@@ -350,10 +397,6 @@ int refine_solve(int m, int n, const double *A, int lda, const double *b, double
 }
 
 // ------------------------------------------- single-launch schedule --------
-struct DevInfo {
-  int cus;
-  long long wclk_khz;
-};
 bool dev_info(DevInfo &d) {
   static DevInfo cache[64];
   static bool have[64];
@@ -369,7 +412,7 @@ bool dev_info(DevInfo &d) {
     have[dev] = true;
   }
   d = cache[dev];
-  return d.cus > 0;
+  return true;
 }
 
 // Columns held by the workgroup holding the most, for panels of bw columns
@@ -463,7 +506,7 @@ int res_launch_rr(ResArgs a, int cus, hipStream_t st) {
 int res_launch_dd(const StepArgs &s, void *sync, double *u, hipStream_t st) {
   using P = PrecDD;
   DevInfo d;
-  if (!dev_info(d)) return 1;
+  if (!dev_info(d) || d.cus <= 0) return 1;
   ResPlan pl;
   if (!res_choose(s.m, s.ncols, d.cus, pl)) return 1;
   ResArgs a;
@@ -534,6 +577,32 @@ int small_launch_dd(const StepArgs &s, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
 }
 
+// Batched systems: one workgroup per system (returns MGS_ERR_DIMS when one
+// system's q vectors do not fit in LDS).  Waves per system: 4 (FP64), 8
+// (dd), 16 (qd), so that a slot of every wave holds a column in registers
+// and several systems share a compute unit.
+template <class P, int NW, int CPW>
+int batched_launch(const BatArgs &a, hipStream_t st) {
+  static_assert(NW * CPW == BAT_MAX_COLS, "every column of [A b] needs a slot");
+  const size_t shmem = sizeof(double) * 2 * P::L * (size_t)a.n * a.m;
+  if (shmem > BAT_LDS_BYTES) return MGS_ERR_DIMS;
+  if (a.batch == 0) return MGS_OK;
+  auto kern = mgs_batched_kernel<P, NW, CPW>;
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)shmem) != hipSuccess)
+    return MGS_ERR_LAUNCH;
+  hipLaunchKernelGGL(kern, dim3(a.batch), dim3(64 * NW), shmem, st, a);
+  return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
+}
+int batched_dispatch(int prec, const BatArgs &a, hipStream_t st) {
+  if (prec == 1) return batched_launch<PrecD, 4, 16>(a, st);
+  if (prec == 2) return batched_launch<PrecDD, 8, 8>(a, st);
+  return batched_launch<PrecQD, 16, 4>(a, st);
+}
+bool batched_fits(int m, int n, int ncols, int prec) {
+  return m <= BAT_MAX_ROWS && ncols <= BAT_MAX_COLS && sizeof(double) * 2 * prec * (size_t)n * m <= BAT_LDS_BYTES;
+}
+
 }  // namespace
 
 extern "C" {
@@ -559,7 +628,9 @@ const char *mgs_status_string(int status) {
 }
 
 int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes) {
-  if (op == MGS_OP_QR64 ? prec != 1 : (prec != 2 && prec != 4)) return MGS_ERR_PREC;
+  if (op == MGS_OP_QR64 ? prec != 1
+                        : (op == MGS_OP_QR || op == MGS_OP_SOLVE ? !prec_ok(prec) : (prec != 2 && prec != 4)))
+    return MGS_ERR_PREC;
   if (n < 1 || m < n || m > (op == MGS_OP_QR64 ? MGS_MAX_ROWS_DD : max_rows(prec))) return MGS_ERR_DIMS;
   if (!bytes) return MGS_ERR_POINTER;
   switch (op) {
@@ -575,7 +646,7 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes) {
 int mgs_qr_schedule(int m, int n, int prec, const double *A, int lda, double *Q, int ldq, double *R, int ldr,
                     const double *b, double *y, double *rho, void *work, size_t work_bytes, int *info,
                     int schedule, mgs_stream_t stream) {
-  if (prec != 2 && prec != 4) return MGS_ERR_PREC;
+  if (!prec_ok(prec)) return MGS_ERR_PREC;
   if (schedule < MGS_SCHED_AUTO || schedule > MGS_SCHED_SMALL) return MGS_ERR_UNSUPPORTED;
   if (n < 1 || m < n || m > max_rows(prec) || lda < m || ldq < m || ldr < n) return MGS_ERR_DIMS;
   if (!aligned8(A) || !aligned8(Q) || !aligned8(R) || !aligned8(info)) return MGS_ERR_POINTER;
@@ -609,7 +680,33 @@ int mgs_qr_schedule(int m, int n, int prec, const double *A, int lda, double *Q,
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int mode = schedule;
   if (mode == MGS_SCHED_AUTO || mode == MGS_SCHED_SMALL) {
-    const int rc = prec == 2 ? small_launch_dd(a, st) : 1;
+    int rc = 1;
+    if (prec == 2) {
+      rc = small_launch_dd(a, st);
+    } else if (batched_fits(m, n, a.ncols, prec)) {
+      // FP64 and qd: the batched kernel on a batch of one.
+      DevInfo d;
+      if (dev_info(d)) {
+        BatArgs ba;
+        ba.batch = 1;
+        ba.m = m;
+        ba.n = n;
+        ba.ncols = a.ncols;
+        ba.A = A;
+        ba.lda = lda;
+        ba.b = b;
+        ba.Q = Q;
+        ba.ldq = ldq;
+        ba.R = R;
+        ba.ldr = ldr;
+        ba.y = a.y;
+        ba.x = nullptr;
+        ba.rho = a.rho;
+        ba.info = info;
+        ba.spin_ticks = d.wclk_khz * 2000;  // 2 s
+        rc = batched_dispatch(prec, ba, st);
+      }
+    }
     if (rc != 1) return rc;
     if (mode == MGS_SCHED_SMALL) return MGS_ERR_DIMS;
   }
@@ -620,6 +717,7 @@ int mgs_qr_schedule(int m, int n, int prec, const double *A, int lda, double *Q,
     if (rc != 1) return rc;
     if (mode == MGS_SCHED_RESIDENT) return MGS_ERR_DIMS;
   }
+  if (prec == 1) return dispatch_shape<PrecD>(a, sh, st);
   if (prec == 2) return dispatch_shape<PrecDD>(a, sh, st);
   return dispatch_shape<PrecQD>(a, sh, st);
 }
@@ -633,11 +731,12 @@ int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq,
 
 int ls_backsolve(int n, int prec, const double *R, int ldr, const double *y, double *x, int *info,
                  mgs_stream_t stream) {
-  if (prec != 2 && prec != 4) return MGS_ERR_PREC;
+  if (!prec_ok(prec)) return MGS_ERR_PREC;
   if (n < 1 || n > max_rows(prec) || ldr < n) return MGS_ERR_DIMS;
   if (!aligned8(R) || !aligned8(y) || !aligned8(x) || !aligned8(info)) return MGS_ERR_POINTER;
   if (x == y) return MGS_ERR_POINTER;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (prec == 1) return backsolve_launch<PrecD>(n, R, ldr, y, x, info, st);
   if (prec == 2) return backsolve_launch<PrecDD>(n, R, ldr, y, x, info, st);
   return backsolve_launch<PrecQD>(n, R, ldr, y, x, info, st);
 }
@@ -645,15 +744,18 @@ int ls_backsolve(int n, int prec, const double *R, int ldr, const double *y, dou
 int ls_solve(int m, int n, int prec, const double *Q, int ldq, const double *R, int ldr,
              const double *b, double *x, void *work, size_t work_bytes, int *info,
              mgs_stream_t stream) {
-  if (prec != 2 && prec != 4) return MGS_ERR_PREC;
+  if (!prec_ok(prec)) return MGS_ERR_PREC;
   if (n < 1 || m < n || m > max_rows(prec) || ldq < m || ldr < n) return MGS_ERR_DIMS;
   if (!aligned8(Q) || !aligned8(R) || !aligned8(b) || !aligned8(x) || !aligned8(info) || !aligned8(work))
     return MGS_ERR_POINTER;
   if (work_bytes < solve_work_bytes(n, prec)) return MGS_ERR_WORKSPACE;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   double *y = static_cast<double *>(work);
-  int rc = prec == 2 ? project_launch<PrecDD>(m, n, Q, ldq, b, y, st) : project_launch<PrecQD>(m, n, Q, ldq, b, y, st);
+  int rc = prec == 1   ? project_launch<PrecD>(m, n, Q, ldq, b, y, st)
+           : prec == 2 ? project_launch<PrecDD>(m, n, Q, ldq, b, y, st)
+                       : project_launch<PrecQD>(m, n, Q, ldq, b, y, st);
   if (rc != MGS_OK) return rc;
+  if (prec == 1) return backsolve_launch<PrecD>(n, R, ldr, y, x, info, st);
   if (prec == 2) return backsolve_launch<PrecDD>(n, R, ldr, y, x, info, st);
   return backsolve_launch<PrecQD>(n, R, ldr, y, x, info, st);
 }
@@ -707,6 +809,44 @@ int mgs_qr64(int m, int n, const double *A, int lda, const double *b, double *Q,
   hipLaunchKernelGGL(copy64_out_kernel, dim3(gx, n + 1), dim3(256), 0, st, m, n, w.Q64, w.R64, Q, ldq, R, ldr,
                      b != nullptr ? y : nullptr);
   return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
+}
+
+int mgs_lstsq_batched(int batch, int m, int n, int prec, const double *A, int lda, const double *b, double *Q,
+                      int ldq, double *R, int ldr, double *y, double *x, double *rho, int *info,
+                      mgs_stream_t stream) {
+  if (!prec_ok(prec)) return MGS_ERR_PREC;
+  const int ncols = n + (b ? 1 : 0);
+  if (batch < 0 || n < 1 || m < n || lda < m || ldq < m || ldr < n) return MGS_ERR_DIMS;
+  if (!batched_fits(m, n, ncols, prec)) return MGS_ERR_DIMS;
+  if (batch == 0) return MGS_OK;  // nothing is read or written (empty tensors may have null pointers)
+  if (!aligned8(A) || !aligned8(Q) || !aligned8(R) || !aligned8(info)) return MGS_ERR_POINTER;
+  if (Q == A && ldq != lda) return MGS_ERR_POINTER;
+  if (b != nullptr) {
+    if (!aligned8(b) || (y == nullptr && x == nullptr)) return MGS_ERR_POINTER;
+    if ((y != nullptr && !aligned8(y)) || (x != nullptr && !aligned8(x)) || (x != nullptr && x == y))
+      return MGS_ERR_POINTER;
+    if (rho != nullptr && !aligned8(rho)) return MGS_ERR_POINTER;
+  }
+  DevInfo d;
+  if (!dev_info(d)) return MGS_ERR_LAUNCH;
+  BatArgs a;
+  a.batch = batch;
+  a.m = m;
+  a.n = n;
+  a.ncols = ncols;
+  a.A = A;
+  a.lda = lda;
+  a.b = b;
+  a.Q = Q;
+  a.ldq = ldq;
+  a.R = R;
+  a.ldr = ldr;
+  a.y = b ? y : nullptr;
+  a.x = b ? x : nullptr;
+  a.rho = b ? rho : nullptr;
+  a.info = info;
+  a.spin_ticks = d.wclk_khz * 2000;  // 2 s
+  return batched_dispatch(prec, a, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -75,7 +75,8 @@ struct ResArgs {
 // Diagnostic builds (-DMGS_TRACE) stamp the wall clock at the steps of the
 // critical chain, per column: 0 poll of the hand-off started, 1 hand-off
 // data arrived, 2 last projection applied, 3 column handed on (stores
-// issued), 4 column normalised and published.
+// issued), 4 column normalised and published, 5 block sums of the last
+// projection past their barrier, 6 square root and reciprocal done.
 constexpr int RES_TRACE_SLOTS = 8;
 #ifdef MGS_TRACE
 #define RES_TRACE(col, slot)                                                                   \
@@ -466,11 +467,13 @@ struct Resident {
       }
     });
     lds_barrier();
+    if (last) RES_TRACE(ps, 5);
     const Rl s2 = P::acc_value_re(xch_tree<0, NW>(1, true));
     const C d = P::acc_value(xch_tree<0, NW>(0, false));
     xb ^= 1;
     Rl rkk, inv;
     P::sqrt_recip(s2, rkk, inv);
+    if (last) RES_TRACE(ps, 6);
 #pragma unroll
     for (int r = 0; r < RR; ++r) u[r] = P::scale(u[r], inv);
     const C rk = P::scale(d, inv);

@@ -17,7 +17,8 @@ of a polynomial system of degree d holds values of modulus 10^(+-d),
 Section 4):
 
 * ``config1`` -- dd, 32 x 32, re/im hi limbs U[-1,1], lo = hi 2^-53 U[-1,1];
-  x_true alike; b = A x_true rounded to dd from the exact sum.
+  x_true alike; b = A x_true rounded to dd from the exact sum
+  (``config1_batch``: systems 0, 1, ... of the same recipe, for batches).
 * ``config2`` -- qd, 320 x 256, limb k = hi 2^(-53k) U_k[-1,1]; b = A x_true
   + noise of modulus 1e-40, rounded to qd from the exact sum.
 * ``config3`` -- dd, 1024 x 1024 systems (64 back to back): re, im ~ N(0,1),
@@ -28,7 +29,10 @@ Section 4):
   of 4 Householder reflectors with complex N(0,1) vectors, sigma geometric
   from 1 to 1e-10; x_true complex N(0,1); b = A x_true rounded to qd from the
   exact sum, so that x_true solves the stored system to about
-  kappa 2^-212 (the reference for the precision form).
+  kappa 2^-212 (the reference for the precision form); with ``tail`` the
+  matrix carries a second limb below FP64 (relative 2^-60), so the FP64
+  factorisation factors only an approximation of it, and b stays exact in
+  qd.
 * ``config5`` -- dd, 512 x 384, A, b, g with N(0,1) hi limbs.
 * ``table2_matrix`` -- 32 x 32 entries r e^{i theta}, theta ~ U[0, 2 pi),
   log10 r ~ U[-g, g] (Section 4, Table 2).
@@ -219,13 +223,35 @@ def dd_matvec_dx(A, x):
 
 
 # ----------------------------------------------------------------- configs --
-def config1():
-    """dd 32 x 32 (configuration 1). Returns dict(A, b, x_true, prec)."""
+def config1(system=0):
+    """dd 32 x 32 (configuration 1; `system` numbers independent draws).
+    Returns dict(A, b, x_true, prec)."""
     m = n = 32
-    A = random_complex(rng(1, 0, 0), (n, m), 2)
-    x = random_complex(rng(1, 0, 1), (n,), 2)
+    A = random_complex(rng(1, system, 0), (n, m), 2)
+    x = random_complex(rng(1, system, 1), (n,), 2)
     b = exact_matvec(A, x, 2)
     return dict(A=A, b=b, x_true=x, prec=2, m=m, n=n)
+
+
+def _config1_arrays(system):
+    d = config1(system)
+    return d["A"], d["b"], d["x_true"]
+
+
+def config1_batch(count, first=0, workers=1):
+    """Systems first .. first+count-1 of configuration 1, stacked on a leading
+    batch axis: dict(A (count,2,2,32,32), b, x_true (count,2,2,32))."""
+    ids = range(first, first + count)
+    if workers > 1 and count > 1:
+        import multiprocessing as mp
+
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_config1_arrays, ids, chunksize=max(1, count // (4 * workers)))
+    else:
+        parts = [_config1_arrays(i) for i in ids]
+    return dict(A=np.ascontiguousarray(np.stack([p[0] for p in parts])),
+                b=np.ascontiguousarray(np.stack([p[1] for p in parts])),
+                x_true=np.ascontiguousarray(np.stack([p[2] for p in parts])), prec=2, m=32, n=32)
 
 
 def config2():
@@ -259,8 +285,15 @@ def config3(system=0, m=1024, n=1024):
                 scales=c)
 
 
-def config4(n=2048, reflectors=4, cond=1e10, workers=1):
-    """Precision-form workload: FP64 A = U diag(sigma) V^H, b exact to qd."""
+def config4(n=2048, reflectors=4, cond=1e10, workers=1, tail=False):
+    """Precision-form workload: FP64 A = U diag(sigma) V^H, b exact to qd.
+
+    With tail=True the matrix also carries information below FP64: entry a
+    becomes a + a 2^-60 u, u ~ U[-1,1] (role 6), a second limb that FP64
+    drops, stored with 2 limbs ("A2") and with 4 ("A4", two zero limbs).
+    Each product of A and x_true then has at most 166 significant bits, so
+    b4 = A x_true is exact in qd (x_true solves the qd system exactly) and
+    b2 is its leading two limbs."""
     g = rng(4, 0, 5)
     sigma = cond ** (-np.arange(n) / (n - 1.0))
     M = np.diag(sigma).astype(np.complex128)
@@ -276,8 +309,18 @@ def config4(n=2048, reflectors=4, cond=1e10, workers=1):
     xg = rng(4, 0, 1)
     x = np.zeros((1, 2, n))
     x[0] = xg.standard_normal((2, n))
-    b4 = exact_matvec(A1, x, 4, workers=workers)
-    return dict(A64=np.ascontiguousarray(A1), b4=b4, x_true=x, sigma=sigma, n=n, m=n)
+    if not tail:
+        b4 = exact_matvec(A1, x, 4, workers=workers)
+        return dict(A64=np.ascontiguousarray(A1), b4=b4, x_true=x, sigma=sigma, n=n, m=n)
+    tg = rng(4, 0, 6)
+    A2 = np.zeros((2,) + A1.shape[1:])
+    A2[0] = A1[0]
+    A2[1] = A1[0] * 2.0 ** -60 * tg.uniform(-1.0, 1.0, A1[0].shape)  # |.| <= ulp(a) / 2: normalised
+    A4 = np.zeros((4,) + A1.shape[1:])
+    A4[:2] = A2
+    b4 = exact_matvec(A2, x, 4, workers=workers)
+    return dict(A64=np.ascontiguousarray(A1), A4=A4, A2=A2, b4=b4, b2=np.ascontiguousarray(b4[:2]), x_true=x,
+                sigma=sigma, n=n, m=n)
 
 
 def config5():

@@ -74,7 +74,8 @@ def _qr(m=8, n=4, prec=2, A=FAKE, lda=8, Q=FAKE + 4096, ldq=8, R=FAKE + 8192, ld
 
 def test_mgs_qr_rejects_bad_arguments():
     assert _qr(prec=3) == -3
-    assert _qr(prec=1) == -3
+    assert _qr(prec=0) == -3
+    assert _qr(prec=5) == -3
     assert _qr(m=3, n=4) == -1
     assert _qr(n=0) == -1
     assert _qr(lda=7) == -1
@@ -135,7 +136,8 @@ def test_ls_adjoint_rejects_bad_arguments():
     assert call(gA=FAKE) == -2        # aliases A
     assert call(gb=FAKE + 64) == -2   # aliases b
     assert call(wb=16) == -4
-    assert _lib.workspace_size(8, 4, 2, _lib.MGS_OP_ADJOINT) == 3 * 256
+    # w, z, r, then 2 x (one chunk) x 8 rows of 32-byte dd accumulators
+    assert _lib.workspace_size(8, 4, 2, _lib.MGS_OP_ADJOINT) == 3 * 256 + 512
 
 
 def test_mgs_qr64_rejects_bad_arguments():
@@ -163,3 +165,46 @@ def test_mgs_qr64_rejects_bad_arguments():
     assert _lib.workspace_size(8, 4, 1, _lib.MGS_OP_QR64) == 768 + 512
     with pytest.raises(_lib.MgsError):
         _lib.workspace_size(8, 4, 2, _lib.MGS_OP_QR64)
+
+
+def test_prec1_workspaces_and_refusals():
+    # complex double (prec 1): QR and SOLVE only; the adjoint and the
+    # precision form stay dd / qd
+    assert _lib.workspace_size(32, 32, 1, _lib.MGS_OP_QR) == 2 * 32 * 8 + 1024
+    assert _lib.workspace_size(32, 32, 1, _lib.MGS_OP_SOLVE) == 512
+    with pytest.raises(_lib.MgsError):
+        _lib.workspace_size(32, 32, 1, _lib.MGS_OP_ADJOINT)
+    with pytest.raises(_lib.MgsError):
+        _lib.workspace_size(32, 32, 1, _lib.MGS_OP_REFINE)
+    L = _lib.lib()
+    assert L.mgs_refine_solve(8, 4, 1, FAKE, 8, FAKE, FAKE + 64, 64, 0.0, 4, None, None, FAKE, 1 << 20, FAKE,
+                              None) == -3
+
+
+def test_mgs_lstsq_batched_rejects_bad_arguments():
+    L = _lib.lib()
+    names = ["batch", "m", "n", "prec", "A", "lda", "b", "Q", "ldq", "R", "ldr", "y", "x", "rho", "info", "stream"]
+    args = [4, 32, 32, 2, FAKE, 32, FAKE + 4096, FAKE + 8192, 32, FAKE + 12288, 32, None, FAKE + 16384, None,
+            FAKE + 20480, None]
+
+    def call(**kw):
+        a = list(args)
+        for k, v in kw.items():
+            a[names.index(k)] = v
+        return L.mgs_lstsq_batched(*a)
+    assert call(prec=3) == -3
+    assert call(batch=-1) == -1
+    assert call(n=0) == -1
+    assert call(m=31) == -1
+    assert call(m=65, lda=65, ldq=65) == -1           # more rows than lanes of a wave
+    assert call(m=64, n=64, lda=64, ldq=64, ldr=64) == -1   # 65 columns of [A b]
+    assert call(lda=31) == -1
+    assert call(ldr=31) == -1
+    # qd: the q vectors of a system must fit in LDS (64 m n bytes)
+    assert call(prec=4, m=64, n=40, lda=64, ldq=64, ldr=40) == -1
+    assert call(A=None) == -2
+    assert call(A=ODD) == -2
+    assert call(info=None) == -2
+    assert call(x=None) == -2                         # b given: y or x required
+    assert call(y=FAKE + 16384) == -2                 # x aliases y
+    assert call(Q=FAKE, ldq=33, m=32) in (-1, -2)

@@ -1,0 +1,189 @@
+"""GPU parity of the batched entry point (mgs_lstsq_batched) and of the
+complex-double (prec 1) path, through the C ABI, against the CPU oracle.
+
+Every system of a batch is compared with the oracle's MGS (Figure 1 on
+[A b], Equation (1)) and back substitution (Figure 3) of that system alone;
+the bar is the one of the single-system tests (about 2^12 units of the
+working precision times max(1, kappa / 100)).  Systems are independent: a
+system's results do not depend on the batch it is in (bitwise).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1210_0800_amd import _lib, api, inputs  # noqa: E402
+from tests._exact import EPS  # noqa: E402
+from tests._parity import TAU, assert_parity, diff, errors  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda:0"))
+
+
+def N(t):
+    return None if t is None else t.cpu().numpy()
+
+
+def run_batch(A, b, **kw):
+    f = api.lstsq_batched(T(A), None if b is None else T(b), **kw)
+    torch.cuda.synchronize()
+    return {k: N(v) for k, v in f.items()}
+
+
+def check_system(A, b, prec, Q, R, x=None, y=None, rho=None, invariants=False):
+    o = oracle.mgs(A, b)
+    assert o["info"] == 0
+    xo = None
+    if b is not None:
+        xo, _ = oracle.backsolve(o["R"], o["y"])
+    e = errors(A, Q, R, o["Q"], o["R"], x, xo, o["rho"] if b is not None else None)
+    assert_parity(e, prec, what=("err_q", "err_r") + (("err_x",) if x is not None else ()))
+    n = A.shape[2]
+    il = np.tril_indices(n, -1)
+    assert np.all(R[:, :, il[1], il[0]] == 0)
+    assert np.all(R[:, 1, np.arange(n), np.arange(n)] == 0)
+    assert np.all(R[0, 0, np.arange(n), np.arange(n)] > 0)
+    tol = TAU[prec] * max(1.0, e["kappa"] / 100.0)
+    if y is not None:
+        nb = np.sqrt(np.sum(b[0] ** 2))
+        assert np.sqrt(np.sum(diff(y, o["y"]) ** 2)) <= 10 * tol * nb
+    if rho is not None:
+        nb = np.sqrt(np.sum(b[0] ** 2))
+        assert abs(float(diff(rho[:, None], o["rho"][:, None])[0])) <= 10 * tol * nb
+    if invariants:
+        ev = oracle.errors(A, Q, R)
+        m = A.shape[3]
+        assert ev[1] <= 4 * m * EPS[prec], ev
+        assert ev[2] <= 10 * e["kappa"] * n * EPS[prec], ev
+    return e
+
+
+def test_config1_batch_against_oracle():
+    """64 systems of configuration 1 (dd 32 x 32) in one call."""
+    d = inputs.config1_batch(64, workers=4)
+    g = run_batch(d["A"], d["b"], with_y=True, with_rho=True)
+    assert np.all(g["info"] == 0)
+    for s in range(64):
+        e = check_system(d["A"][s], d["b"][s], 2, g["Q"][s], g["R"][s], g["x"][s], g["y"][s], g["rho"][s],
+                         invariants=(s % 16 == 0))
+        # square consistent systems: x_true recovered
+        dx = np.abs(diff(g["x"][s], d["x_true"][s]))
+        assert dx.max() <= 1e-27 * e["kappa"]
+
+
+def test_batch_members_are_independent():
+    """A system's results are bitwise those of a batch of one, wherever it sits."""
+    d = inputs.config1_batch(9, workers=1)
+    g = run_batch(d["A"], d["b"])
+    for s in (0, 4, 8):
+        one = run_batch(d["A"][s:s + 1], d["b"][s:s + 1])
+        for k in ("Q", "R", "x"):
+            assert np.array_equal(one[k][0], g[k][s]), (s, k)
+    g2 = run_batch(d["A"], d["b"])
+    for k in ("Q", "R", "x", "info"):
+        assert np.array_equal(g[k], g2[k])
+
+
+SHAPES = {
+    1: [(1, 1), (5, 3), (17, 16), (32, 32), (33, 7), (64, 40), (64, 63)],
+    2: [(1, 1), (5, 3), (17, 16), (32, 32), (33, 7), (64, 40), (64, 63)],
+    4: [(1, 1), (9, 3), (16, 16), (32, 32), (48, 40), (50, 50)],
+}
+CASES = [(p, m, n) for p in (1, 2, 4) for (m, n) in SHAPES[p]]
+
+
+@pytest.mark.parametrize("prec,m,n", CASES)
+def test_random_batches_against_oracle(prec, m, n):
+    B = 5
+    probs = [inputs.random_problem(prec, m, n, seed=100 * s + m + n, config=60) for s in range(B)]
+    A = np.stack([p["A"] for p in probs])
+    b = np.stack([p["b"] for p in probs])
+    g = run_batch(A, b, with_y=True, with_rho=True)
+    assert np.all(g["info"] == 0), g["info"]
+    for s in range(B):
+        check_system(A[s], b[s], prec, g["Q"][s], g["R"][s], g["x"][s], g["y"][s], g["rho"][s],
+                     invariants=(s == 0))
+
+
+@pytest.mark.parametrize("prec", [1, 2, 4])
+def test_qr_only_in_place(prec):
+    probs = [inputs.random_problem(prec, 30, 24, seed=s, config=61) for s in range(4)]
+    A = np.stack([p["A"] for p in probs])
+    g = run_batch(A, None)
+    assert g["x"] is None and np.all(g["info"] == 0)
+    At = T(A)
+    f = api.lstsq_batched(At, None, Q=At)
+    torch.cuda.synchronize()
+    assert np.array_equal(N(At), g["Q"]) and np.array_equal(N(f["R"]), g["R"])
+    for s in range(4):
+        check_system(A[s], None, prec, g["Q"][s], g["R"][s])
+
+
+@pytest.mark.parametrize("prec", [1, 2, 4])
+def test_bad_column_reports_info_per_system(prec):
+    probs = [inputs.random_problem(prec, 20, 12, seed=s, config=62) for s in range(4)]
+    A = np.stack([p["A"] for p in probs])
+    b = np.stack([p["b"] for p in probs])
+    A[1, :, :, 5] = 0.0          # zero column 6 in system 1
+    A[2, 0, 0, 9, 3] = np.nan    # NaN in column 10 of system 2
+    g = run_batch(A, b)
+    assert list(g["info"]) == [0, 6, 10, 0]
+    for s in (0, 3):
+        check_system(A[s], b[s], prec, g["Q"][s], g["R"][s], g["x"][s])
+
+
+def test_empty_batch_and_refusals():
+    A = torch.zeros((0, 2, 2, 8, 8), dtype=torch.float64, device="cuda:0")
+    f = api.lstsq_batched(A, torch.zeros((0, 2, 2, 8), dtype=torch.float64, device="cuda:0"))
+    torch.cuda.synchronize()
+    assert f["info"].numel() == 0
+    for prec, m, n in ((2, 65, 20), (2, 64, 64), (4, 64, 40)):
+        q = inputs.random_problem(prec, m, n, seed=3, config=63)
+        with pytest.raises(_lib.MgsError) as err:
+            api.lstsq_batched(T(q["A"][None]), T(q["b"][None]))
+        assert err.value.status == -1
+
+
+# ------------------------------------------------ complex double, prec 1 --
+# The paper's third precision (Table 4: n = 16 .. 256, square systems).
+FP64_SHAPES = [(16, 16), (32, 32), (80, 80), (128, 128), (256, 256), (300, 200), (1030, 40)]
+
+
+@pytest.mark.parametrize("m,n", FP64_SHAPES)
+def test_fp64_lstsq_against_oracle(m, n):
+    p = inputs.random_problem(1, m, n, seed=m + n, config=64)
+    A, b = p["A"], p["b"]
+    o = oracle.mgs(A, b)
+    xo, _ = oracle.backsolve(o["R"], o["y"])
+    for sched in (None, "panel"):
+        f = api.lstsq(T(A), T(b), schedule=sched)
+        torch.cuda.synchronize()
+        assert int(f["info"].item()) == 0 and int(f["info_backsolve"].item()) == 0
+        e = errors(A, N(f["Q"]), N(f["R"]), o["Q"], o["R"], N(f["x"]), xo, o["rho"])
+        assert_parity(e, 1)
+    # y by sequential projections (ls_solve), the same operations
+    x2, info = api.ls_solve(f["Q"], f["R"], T(b))
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    xo2, _ = oracle.ls_solve(o["Q"], o["R"], b)
+    e = errors(A, N(f["Q"]), N(f["R"]), o["Q"], o["R"], N(x2), xo2, None)
+    assert_parity(e, 1)
+    if m * n <= 128 * 128:
+        ev = oracle.errors(A, N(f["Q"]), N(f["R"]))
+        assert ev[1] <= 4 * m * EPS[1], ev
+        assert ev[2] <= 10 * e["kappa"] * n * EPS[1], ev
+
+
+def test_fp64_backsolve_against_oracle():
+    p = inputs.random_problem(1, 200, 200, seed=5, config=65)
+    o = oracle.mgs(p["A"], p["b"])
+    x, info = api.ls_backsolve(T(o["R"]), T(o["y"]))
+    torch.cuda.synchronize()
+    xo, _ = oracle.backsolve(o["R"], o["y"])
+    assert int(info.item()) == 0
+    d = diff(N(x), xo)
+    assert np.sqrt(np.sum(d ** 2)) <= 1e-11 * np.sqrt(np.sum(xo ** 2))

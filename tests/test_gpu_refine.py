@@ -12,6 +12,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+import oracle  # noqa: E402
 from paper_1210_0800_amd import api, inputs  # noqa: E402
 from tests._parity import diff, value  # noqa: E402
 
@@ -63,12 +64,63 @@ def test_refined_matches_plain_accuracy_n256(L):
     assert plain <= (1e-19 if L == 2 else 1e-49)
 
 
+@pytest.mark.parametrize("L", [2, 4])
+def test_refine_against_the_oracle_refinement_n256(L):
+    """The same method in the oracle (FP64 blocked MGS with panels of 64,
+    residual in qd, projections replayed): same outcome, iteration counts
+    within one, solutions equal to the working precision."""
+    d = inputs.config4(256)
+    A = planar(d["A64"], L)
+    b = d["b4"][:L].copy()
+    r = api.refine_lstsq(T(A), T(b), max_iter=30)
+    torch.cuda.synchronize()
+    o = oracle.refine(A, b, block=64, max_iter=30)
+    print("n=256 L=%d gpu iters %d oracle iters %d" % (L, int(r["iters"].item()), o["iters"]))
+    assert int(r["info"].item()) == 0 and o["info"] == 0
+    assert abs(int(r["iters"].item()) - o["iters"]) <= 1
+    assert rel_err(r["x"].cpu().numpy(), o["x"]) <= (1e-27 if L == 2 else 1e-57)
+
+
 def test_refined_dd_config4_2048():
     d = inputs.config4(2048, workers=8)
     plain, refined, iters, info, est = solve_both(d, 2)
     print("n=2048 dd plain %.3e refined %.3e iters %d info %d" % (plain, refined, iters, info))
     assert info == 0 and iters <= 12
     assert refined <= plain
+
+
+def solve_stored(A, b, x_true, max_iter=30):
+    """Plain MGS and refined solutions of the stored system (A, b)."""
+    Ag, bg = T(A), T(b)
+    f = api.lstsq(Ag, bg)
+    r = api.refine_lstsq(Ag, bg, max_iter=max_iter)
+    torch.cuda.synchronize()
+    assert int(f["info"].item()) == 0
+    plain = rel_err(f["x"].cpu().numpy(), x_true)
+    refined = rel_err(r["x"].cpu().numpy(), x_true)
+    return plain, refined, int(r["iters"].item()), int(r["info"].item()), float(r["err_est"].item())
+
+
+@pytest.fixture(scope="module")
+def config4_tail():
+    return inputs.config4(2048, workers=16, tail=True)
+
+
+@pytest.mark.parametrize("L", [2, 4])
+def test_refined_with_subfp64_matrix_2048(config4_tail, L):
+    """A carries a limb below FP64 (relative 2^-60), so the FP64 factors
+    are those of an approximation of A; the refinement (residual of the
+    full A) still reaches the plain method's error, converging.  x_true
+    solves the qd system exactly; the dd right-hand side is rounded."""
+    d = config4_tail
+    A, b = (d["A2"], d["b2"]) if L == 2 else (d["A4"], d["b4"])
+    plain, refined, iters, info, est = solve_stored(A, b, d["x_true"])
+    print("n=2048 tail L=%d plain %.3e refined %.3e iters %d info %d est %.2e" % (L, plain, refined, iters, info,
+                                                                                   est))
+    assert info == 0 and 1 <= iters <= 25
+    assert np.isfinite(est) and est < 1.0
+    assert refined <= plain
+    assert plain <= (1e-19 if L == 2 else 1e-49)
 
 
 def test_refinement_reports_failure_to_converge():

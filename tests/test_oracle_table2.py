@@ -46,3 +46,23 @@ def test_table2_ranges(g, prec, me, Me):
     logs = np.array(logs)
     assert logs.min() >= me - 0.5 and logs.max() <= Me + 0.5, (g, prec, logs)
     assert me - 0.25 <= np.median(logs) <= Me + 0.25, (g, prec, np.median(logs))
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_emax_batch_matches_errors(L):
+    """The batched e_max (one system per thread) is errors()[0], bitwise."""
+    As, Qs, Rs = [], [], []
+    for s in range(5):
+        A = inputs.table2_matrix(inputs.rng(21, s, L), 8 * (s + 1), L)
+        o = oracle.mgs(A)
+        As.append(A)
+        Qs.append(o["Q"])
+        Rs.append(o["R"])
+    As, Qs, Rs = np.stack(As), np.stack(Qs), np.stack(Rs)
+    e = oracle.emax_batch(As, Qs, Rs, nthreads=3)
+    ref = np.array([oracle.errors(As[s], Qs[s], Rs[s])[0] for s in range(5)])
+    assert np.array_equal(e, ref)
+    # a planted error in one entry of R moves only that system's e_max
+    Rs[2, 0, 0, 7, 3] *= 1.0 + 2.0 ** -4
+    e2 = oracle.emax_batch(As, Qs, Rs, nthreads=2)
+    assert np.array_equal(np.delete(e2, 2), np.delete(e, 2)) and e2[2] > 100 * e[2]
