@@ -123,7 +123,9 @@ def test_dd_small_schedule_in_place_and_refusals():
     f2 = api.mgs_qr(Ain, Q=Ain, schedule="small")
     torch.cuda.synchronize()
     assert np.array_equal(N(Ain), Q1) and np.array_equal(N(f2["R"]), R1)
-    for prec, m, n in ((2, 65, 20), (2, 64, 64), (4, 32, 32)):
+    # refused: more rows than lanes, more than 64 columns of [A b], and (qd)
+    # q vectors beyond the LDS budget of the one-workgroup kernel
+    for prec, m, n in ((2, 65, 20), (2, 64, 64), (4, 64, 45), (1, 70, 10)):
         q = inputs.random_problem(prec, m, n, seed=3, config=55)
         with pytest.raises(_lib.MgsError) as err:
             api.mgs_qr(T(q["A"]), T(q["b"]), schedule="small")
