@@ -6,7 +6,9 @@
 // block as soon as x_c is published, in descending c, then solves its own
 // diagonal block: the lane of row c forms x_c (times the reciprocal of
 // r_cc, formed up front), every lane gets it by readlane, the owner lane
-// publishes it, and the rows above c in the block receive r_ic x_c.  So
+// publishes it, and the rows above c in the block receive r_ic x_c.  The
+// entries of R (and of x above the block) are loaded eight columns ahead,
+// so the loads stay off the serial chain.  So
 // every y_i receives r_ic x_c in the order c = n, n-1, ..., i+1 with the
 // operations of the column-oriented loop, and x is bitwise that of the
 // one-workgroup kernel; only the schedule differs: the blocks below are
@@ -26,8 +28,8 @@
 
 namespace mgsq {
 
-constexpr int BP_ROWS = 64;   // rows per workgroup (one wave)
-constexpr int BP_BATCH = 8;   // x entries polled at once
+constexpr int BP_ROWS = 64;  // rows per workgroup (one wave)
+constexpr int BP_RING = 8;   // columns of R (and entries of x) loaded ahead
 
 // x := empty marker (all planes), info := 0; nothing when *skip != 0.
 template <int L>
@@ -83,50 +85,76 @@ __global__ __launch_bounds__(BP_ROWS) void backsolve_pipe_kernel(int n, const do
     if (!P::ok_norm(d.re) && info != nullptr) info_first_bad(info, i + 1);
     inv = P::recip(d.re);
   }
-  // 1. Columns above the block, descending, each as soon as x_c is out.
+  // R(i, col) of this lane's row for the columns the lane applies: above the
+  // block every row, inside it the rows above col.
+  auto rload = [&](int col) __attribute__((always_inline)) {
+    const bool use = mine && (col >= r1 || (col >= r0 && i < col));
+    return use ? P::load(R + (size_t)col * ldr + i, planeR) : P::czero();
+  };
+  // Rings of BP_RING columns in flight: slot t serves the columns
+  // top - t, top - t - BP_RING, ... (static register indices).
+  C rb[BP_RING];  // the block's own columns r1-1, r1-2, ...
+#pragma unroll
+  for (int t = 0; t < BP_RING; ++t) rb[t] = r1 - 1 - t > r0 ? rload(r1 - 1 - t) : P::czero();
+  // 1. Columns above the block, descending, each once x_c is out; R and x
+  // loaded BP_RING columns ahead.
   const long long t0 = wall_clock64();
-  int c = n - 1;
-  while (c >= r1) {
-    const int cnt = c - r1 + 1 < BP_BATCH ? c - r1 + 1 : BP_BATCH;
-    C rv[BP_BATCH];
+  {
+    C ra[BP_RING], xa[BP_RING];
 #pragma unroll
-    for (int t = 0; t < BP_BATCH; ++t)
-      rv[t] = (t < cnt && mine) ? P::load(R + (size_t)(c - t) * ldr + i, planeR) : P::czero();
-    C xv[BP_BATCH];
-    int avail = 0;
-    bool gap = false;
-#pragma unroll
-    for (int t = 0; t < BP_BATCH; ++t) {
+    for (int t = 0; t < BP_RING; ++t) {
+      const int col = n - 1 - t;
       bool miss = false;
-      xv[t] = t < cnt ? bs_coh_load<P>(x + (c - t), (size_t)n, miss) : P::czero();
-      // available: present in every lane, and every later entry too
-      const bool here = t < cnt && __ballot(miss) == 0;
-      gap = gap || !here;
-      if (!gap) avail = t + 1;
+      ra[t] = col >= r1 ? rload(col) : P::czero();
+      xa[t] = col >= r1 ? bs_coh_load<P>(x + col, (size_t)n, miss) : P::czero();
     }
+    int c = n - 1;
+    while (c >= r1) {
 #pragma unroll
-    for (int t = 0; t < BP_BATCH; ++t)
-      if (t < avail && mine) P::upd(yv, rv[t], xv[t]);
-    c -= avail;
-    if (avail == 0) {
-      if (wall_clock64() - t0 > spin_ticks) {
-        if (lane == 0 && info != nullptr)
-          __hip_atomic_store(info, MGS_INFO_SYNC_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return;
+      for (int t = 0; t < BP_RING; ++t) {
+        if (c >= r1) {
+          while (true) {  // x_c, unless the early load already saw it
+            bool miss = false;
+            const double *pv = reinterpret_cast<const double *>(&xa[t]);
+#pragma unroll
+            for (int q = 0; q < 2 * P::L; ++q) miss = miss || __double_as_longlong(pv[q]) == RES_EMPTY;
+            if (__ballot(miss) == 0) break;
+            if (wall_clock64() - t0 > spin_ticks) {
+              if (lane == 0 && info != nullptr)
+                __hip_atomic_store(info, MGS_INFO_SYNC_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              return;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            bool m2 = false;
+            xa[t] = bs_coh_load<P>(x + c, (size_t)n, m2);
+          }
+          if (mine) P::upd(yv, ra[t], xa[t]);
+          const int cn = c - BP_RING;
+          if (cn >= r1) {
+            bool m3 = false;
+            ra[t] = rload(cn);
+            xa[t] = bs_coh_load<P>(x + cn, (size_t)n, m3);
+          }
+          --c;
+        }
       }
-      __builtin_amdgcn_s_sleep(1);
     }
   }
   // 2. The block itself: x_c from its lane, broadcast, published, applied
-  // to the rows above it (R column c read one step ahead).
-  C rn = (r1 - 1 > r0 && lane < r1 - 1 - r0) ? P::load(R + (size_t)(r1 - 1) * ldr + i, planeR) : P::czero();
-#pragma unroll 1
-  for (int cc = r1 - 1; cc >= r0; --cc) {
-    const C rc = rn;
-    if (cc - 1 > r0 && lane < cc - 1 - r0) rn = P::load(R + (size_t)(cc - 1) * ldr + i, planeR);
-    const C xk = bs_readlane<P>(P::scale(yv, inv), cc - r0);
-    if (lane == cc - r0) bs_coh_store<P>(x + cc, (size_t)n, xk);
-    if (lane < cc - r0) P::upd(yv, rc, xk);
+  // to the rows above it (R from the ring, BP_RING columns ahead).
+  int cc = r1 - 1;
+  while (cc >= r0) {
+#pragma unroll
+    for (int t = 0; t < BP_RING; ++t) {
+      if (cc >= r0) {
+        const C xk = bs_readlane<P>(P::scale(yv, inv), cc - r0);
+        if (lane == cc - r0) bs_coh_store<P>(x + cc, (size_t)n, xk);
+        if (lane < cc - r0) P::upd(yv, rb[t], xk);
+        const int cn = cc - BP_RING;
+        if (cn > r0) rb[t] = rload(cn);
+        --cc;
+      }
+    }
   }
 }
 
