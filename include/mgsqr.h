@@ -122,6 +122,24 @@ int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq,
            const double *b, double *y, double *rho, void *work, size_t work_bytes, int *info,
            mgs_stream_t stream);
 
+/*
+ * mgs_qr_noalloc -- mgs_qr for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation): no workspace argument; the workspace lives in a fixed
+ * device array of MGS_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * GPU it runs on until the process ends.  Enough for every shape mgs_qr
+ * accepts (the largest need is dd 1024 x 1024 with b: 32 MiB + 33 KiB);
+ * a shape that would need more returns MGS_ERR_WORKSPACE.  Calls no
+ * allocating routine.  Every call on one GPU shares that GPU's array, so
+ * calls that may overlap in time on the same GPU (different streams or
+ * threads) race: the caller serialises them.  Each call initialises what it
+ * uses (counters, hand-off buffer) itself.  Arguments, results and status
+ * otherwise as mgs_qr.
+ */
+#define MGS_NOALLOC_SCRATCH_BYTES (33u * 1024u * 1024u)
+int mgs_qr_noalloc(int m, int n, int prec, const double *A, int lda, double *Q, int ldq, double *R, int ldr,
+                   const double *b, double *y, double *rho, int *info, mgs_stream_t stream);
+
 /* Schedules of mgs_qr_schedule. */
 enum { MGS_SCHED_AUTO = 0, MGS_SCHED_PANEL = 1, MGS_SCHED_RESIDENT = 2, MGS_SCHED_SMALL = 3 };
 

@@ -19,7 +19,8 @@ MGS_OP_QR64 = 4
 MGS_MAX_ROWS = {1: 4096, 2: 4096, 4: 2048}
 
 EXPORTS = ("mgs_abi_version", "mgs_status_string", "mgs_workspace_size", "mgs_qr", "mgs_qr_schedule",
-           "ls_solve", "ls_backsolve", "ls_adjoint", "mgs_refine_solve", "mgs_qr64", "mgs_lstsq_batched")
+           "ls_solve", "ls_backsolve", "ls_adjoint", "mgs_refine_solve", "mgs_qr64", "mgs_lstsq_batched",
+           "mgs_qr_noalloc")
 SCHEDULES = {"auto": 0, "panel": 1, "resident": 2, "small": 3}
 
 _lib = None
@@ -62,6 +63,8 @@ def lib():
         L.mgs_qr64.restype = I
         L.mgs_lstsq_batched.argtypes = [I, I, I, I, P, I, P, P, I, P, I, P, P, P, P, P]
         L.mgs_lstsq_batched.restype = I
+        L.mgs_qr_noalloc.argtypes = [I, I, I, P, I, P, I, P, I, P, P, P, P, P]
+        L.mgs_qr_noalloc.restype = I
         _lib = L
     return _lib
 

@@ -99,6 +99,36 @@ def mgs_qr(A, b=None, *, Q=None, R=None, y=None, rho=None, info=None, work=None,
     return dict(Q=Q, R=R, y=y, rho=rho, info=info)
 
 
+def mgs_qr_noalloc(A, b=None, *, Q=None, R=None, y=None, rho=None, info=None, with_rho=True):
+    """mgs_qr without a workspace argument (mgs_qr_noalloc): the library's
+    fixed device array serves as workspace.  Calls that may overlap in time
+    on one GPU race on that array; serialise them."""
+    _check_planar("A", A, ndim=4)
+    prec, _, n, m = A.shape
+    dev = A.device
+    Q = torch.empty_like(A) if Q is None else Q
+    _check_planar("Q", Q, prec, 4, shape=A.shape, device=dev)
+    R = torch.empty((prec, 2, n, n), dtype=torch.float64, device=dev) if R is None else R
+    _check_planar("R", R, prec, 4, shape=(prec, 2, n, n), device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev) if info is None else info
+    _check_info(info, dev)
+    if b is not None:
+        _check_planar("b", b, prec, 3, shape=(prec, 2, m), device=dev)
+        y = torch.empty((prec, 2, n), dtype=torch.float64, device=dev) if y is None else y
+        _check_planar("y", y, prec, 3, shape=(prec, 2, n), device=dev)
+        if with_rho and rho is None:
+            rho = torch.empty(prec, dtype=torch.float64, device=dev)
+        if rho is not None and (not isinstance(rho, torch.Tensor) or rho.dtype != torch.float64 or
+                                rho.numel() != prec or rho.device != dev or not rho.is_contiguous()):
+            raise ValueError("rho must be a contiguous float64 tensor of %d limbs on %s" % (prec, dev))
+    else:
+        y = rho = None
+    st = _lib.lib().mgs_qr_noalloc(m, n, prec, _ptr(A), m, _ptr(Q), m, _ptr(R), n, _ptr(b), _ptr(y), _ptr(rho),
+                                   _ptr(info), _stream(A))
+    _lib.check("mgs_qr_noalloc", st)
+    return dict(Q=Q, R=R, y=y, rho=rho, info=info)
+
+
 def ls_backsolve(R, y, *, x=None, info=None):
     """x = R^-1 y by the column-oriented back substitution of Figure 3."""
     _check_planar("R", R, ndim=4)

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "adjoint_kernels.hpp"
 #include "backsolve_kernels.hpp"
@@ -16,6 +17,13 @@
 #include "small_kernels.hpp"
 
 using namespace mgsq;
+
+// Workspace of mgs_qr_noalloc: a fixed device array, one copy per GPU the
+// code object is loaded on, held until the process ends.  Host code never
+// uses this name as an address (it denotes a host-side stand-in): the
+// device address comes from hipGetSymbolAddress (scratch_address below).
+static_assert(MGS_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) unsigned char scratch[MGS_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -603,6 +611,28 @@ bool batched_fits(int m, int n, int ncols, int prec) {
   return m <= BAT_MAX_ROWS && ncols <= BAT_MAX_COLS && sizeof(double) * 2 * prec * (size_t)n * m <= BAT_LDS_BYTES;
 }
 
+// ------------------------------------------------ allocation-free QR ----
+// mgs_qr_noalloc keeps its workspace in `scratch` instead of a
+// caller-supplied buffer; kernels get the device address from
+// hipGetSymbolAddress, taken once per device with that device current.
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES];
+
+// The current device's address of `scratch` (nullptr on failure).
+void *scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -727,6 +757,18 @@ int mgs_qr(int m, int n, int prec, const double *A, int lda, double *Q, int ldq,
            mgs_stream_t stream) {
   return mgs_qr_schedule(m, n, prec, A, lda, Q, ldq, R, ldr, b, y, rho, work, work_bytes, info, MGS_SCHED_AUTO,
                          stream);
+}
+
+int mgs_qr_noalloc(int m, int n, int prec, const double *A, int lda, double *Q, int ldq, double *R, int ldr,
+                   const double *b, double *y, double *rho, int *info, mgs_stream_t stream) {
+  if (!prec_ok(prec)) return MGS_ERR_PREC;
+  if (n < 1 || m < n || m > max_rows(prec) || lda < m || ldq < m || ldr < n) return MGS_ERR_DIMS;
+  const size_t need = qr_work_bytes(m, n, prec);
+  if (need > MGS_NOALLOC_SCRATCH_BYTES) return MGS_ERR_WORKSPACE;
+  void *work = scratch_address();
+  if (work == nullptr) return MGS_ERR_LAUNCH;
+  return mgs_qr_schedule(m, n, prec, A, lda, Q, ldq, R, ldr, b, y, rho, work, MGS_NOALLOC_SCRATCH_BYTES, info,
+                         MGS_SCHED_AUTO, stream);
 }
 
 int ls_backsolve(int n, int prec, const double *R, int ldr, const double *y, double *x, int *info,
