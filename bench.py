@@ -184,7 +184,10 @@ def precision_form(torch, api, n=2048, reps=2):
 # The paper's Tesla C2050 figures (Table 5: 10,000 runs of MGS followed by
 # one back substitution, square random complex matrices), as solves/s.
 PAPER_C2050_SOLVES_PER_S = {("dd", 32): 10000 / 22.44, ("dd", 80): 10000 / 79.11,
-                            ("qd", 32): 10000 / 155.32, ("qd", 80): 10000 / 597.47}
+                            ("qd", 32): 10000 / 155.32, ("qd", 80): 10000 / 597.47,
+                            # Table 4: complex double
+                            ("d", 32): 10000 / 6.52, ("d", 80): 10000 / 22.89, ("d", 128): 10000 / 49.10,
+                            ("d", 256): 10000 / 234.29}
 
 
 def paper_context(torch, api, solves=2000):
@@ -196,9 +199,9 @@ def paper_context(torch, api, solves=2000):
     stream = torch.cuda.current_stream(dev)
     out = {"protocol": "%d back-to-back MGS on [A b] + back substitution, square random complex A "
                        "(re/im of every limb level ~ U[-1,1]), one stream" % solves,
-           "paper_hardware": "NVIDIA Tesla C2050 (1147 MHz), CUDA 4.0; paper Table 5"}
-    for prec, name in ((2, "dd"), (4, "qd")):
-        for n in (32, 80):
+           "paper_hardware": "NVIDIA Tesla C2050 (1147 MHz), CUDA 4.0; paper Tables 4 (double) and 5 (dd, qd)"}
+    for prec, name, sizes in ((1, "d", (32, 80, 128, 256)), (2, "dd", (32, 80)), (4, "qd", (32, 80))):
+        for n in sizes:
             p = inputs.random_problem(prec, n, n, seed=n, config=80)
             A, b = torch.from_numpy(p["A"]).to(dev), torch.from_numpy(p["b"]).to(dev)
             Q = torch.empty_like(A)
@@ -338,6 +341,52 @@ def batched(torch, api, count=10000, reps=5):
     return out
 
 
+# FP64 flops of one qd 1024 x 1024 factorisation of [A b] (per-panel
+# schedule), counted by rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64
+# lanes, FMA = 2) over all step launches of one mgs_qr call; None until
+# counted (see profiles/).
+QD1024_FLOPS = None
+
+
+def qd_large(torch, api, n=1024, reps=2):
+    """Plain qd MGS on [A b] + back substitution at n = 1024 (random square
+    A, every limb level U[-1,1]): time per solve and, when the instruction
+    counts are known, the FP64 rate of the factorisation."""
+    from paper_1210_0800_amd import inputs
+
+    dev = torch.device("cuda:0")
+    p = inputs.random_problem(4, n, n, seed=7, config=85)
+    A, b = torch.from_numpy(p["A"]).to(dev), torch.from_numpy(p["b"]).to(dev)
+    Q = torch.empty_like(A)
+    R = torch.empty((4, 2, n, n), dtype=torch.float64, device=dev)
+    y = torch.empty((4, 2, n), dtype=torch.float64, device=dev)
+    x = torch.empty_like(y)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    info2 = torch.empty(1, dtype=torch.int32, device=dev)
+    work = api.workspace(n, n, 4, 0, dev)
+    stream = torch.cuda.current_stream(dev)
+    api.mgs_qr(A, b, Q=Q, R=R, y=y, info=info, work=work)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tq = tb = 0.0
+    for _ in range(reps):
+        ev[0].record(stream)
+        api.mgs_qr(A, b, Q=Q, R=R, y=y, info=info, work=work)
+        ev[1].record(stream)
+        api.ls_backsolve(R, y, x=x, info=info2)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        tq += ev[0].elapsed_time(ev[1]) / reps
+        tb += ev[1].elapsed_time(ev[2]) / reps
+    out = {"mgs_qr_ms": tq, "backsolve_ms": tb, "solves_per_s": 1e3 / (tq + tb), "info": int(info.item())}
+    if QD1024_FLOPS is not None and n == 1024:
+        achieved = QD1024_FLOPS / (tq * 1e-3) / 1e12
+        out.update(flops_counted=QD1024_FLOPS, achieved_tflops=achieved, frac_fp64_peak=achieved / FP64_PEAK_TFLOPS)
+    print("bench: qd %dx%d plain: factorisation %.1f ms, back substitution %.2f ms" % (n, n, tq, tb),
+          file=sys.stderr, flush=True)
+    return out
+
+
 def copy_probe(nbytes):
     import torch
 
@@ -361,6 +410,7 @@ def main():
     ap.add_argument("--only-precision-form", action="store_true")
     ap.add_argument("--only-context", action="store_true")
     ap.add_argument("--only-batched", action="store_true")
+    ap.add_argument("--only-qd-large", action="store_true")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -372,6 +422,13 @@ def main():
 
         print(json.dumps({"paper_context": paper_context(torch, api), "workloads": workloads(torch, api)}),
               flush=True)
+        return
+    if args.only_qd_large:
+        import torch
+
+        from paper_1210_0800_amd import api
+
+        print(json.dumps({"qd_1024x1024": qd_large(torch, api)}), flush=True)
         return
     if args.only_batched:
         import torch
@@ -486,6 +543,7 @@ def main():
         out["paper_context"] = paper_context(torch, api)
         out["workloads"] = workloads(torch, api)
         out["batched"] = batched(torch, api)
+        out["qd_1024x1024"] = qd_large(torch, api)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host[:4])
     print(json.dumps(out), flush=True)

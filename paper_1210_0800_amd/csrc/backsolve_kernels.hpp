@@ -65,97 +65,165 @@ __device__ __forceinline__ void bs_coh_store(double *p, size_t plane, const type
   for (int q = 0; q < NP; ++q) coh_store(p + (size_t)q * plane, t[q]);
 }
 
+// True when any limb of v carries the empty marker.
+template <class P>
+__device__ __forceinline__ bool bs_empty(const typename P::C &v) {
+  bool miss = false;
+  const double *pv = reinterpret_cast<const double *>(&v);
+#pragma unroll
+  for (int q = 0; q < 2 * P::L; ++q) miss = miss || __double_as_longlong(pv[q]) == RES_EMPTY;
+  return miss;
+}
+
+// v when pick, else w, elementwise (selects, no branch).
+template <class P>
+__device__ __forceinline__ typename P::C bs_pick(bool pick, const typename P::C &v, const typename P::C &w) {
+  typename P::C r;
+  double *pr = reinterpret_cast<double *>(&r);
+  const double *pv = reinterpret_cast<const double *>(&v);
+  const double *pw = reinterpret_cast<const double *>(&w);
+#pragma unroll
+  for (int q = 0; q < 2 * P::L; ++q) pr[q] = pick ? pv[q] : pw[q];
+  return r;
+}
+
+// Memory operations in the loops below are unconditional (addresses
+// clamped into the arrays, unused values discarded by selects) and the loops
+// run whole rings, so that the compiler can count the loads in flight and
+// wait only for the one a step consumes.
 template <class P>
 __global__ __launch_bounds__(BP_ROWS) void backsolve_pipe_kernel(int n, const double *R, int ldr, size_t planeR,
                                                                  const double *y, size_t planeY, double *x,
-                                                                 int *info, const int *skip, long long spin_ticks) {
+                                                                 int *info, const int *skip, long long spin_ticks,
+                                                                 long long *trace) {
   if (skip != nullptr && *skip != 0) return;
   using C = typename P::C;
   using Rl = typename P::R;
   const int lane = threadIdx.x;
   const int r0 = blockIdx.x * BP_ROWS;
+#ifdef MGS_TRACE
+  // diagnostic builds: wall-clock stamps per workgroup (start, phase 1 done,
+  // phase 2 done)
+  if (trace != nullptr && lane == 0) trace[blockIdx.x * 4] = (long long)wall_clock64();
+#else
+  (void)trace;
+#endif
   const int r1 = r0 + BP_ROWS < n ? r0 + BP_ROWS : n;
   const int i = r0 + lane;
   const bool mine = i < r1;
-  C yv = P::czero();
-  Rl inv = P::rzero();
-  if (mine) {
-    yv = P::load(y + i, planeY);
-    const C d = P::load(R + (size_t)i * ldr + i, planeR);
-    if (!P::ok_norm(d.re) && info != nullptr) info_first_bad(info, i + 1);
-    inv = P::recip(d.re);
+  const int ic = mine ? i : n - 1;  // clamped row for loads
+  C yv = P::load(y + ic, planeY);
+  const C dg = P::load(R + (size_t)ic * ldr + ic, planeR);
+  Rl inv = P::recip(dg.re);
+  if (!mine) {
+    yv = P::czero();
+    inv = P::rzero();
   }
-  // R(i, col) of this lane's row for the columns the lane applies: above the
-  // block every row, inside it the rows above col.
+  if (mine && !P::ok_norm(dg.re) && info != nullptr) info_first_bad(info, i + 1);
+  // R(i, col) for this lane's row; col clamped into [0, n).
   auto rload = [&](int col) __attribute__((always_inline)) {
-    const bool use = mine && (col >= r1 || (col >= r0 && i < col));
-    return use ? P::load(R + (size_t)col * ldr + i, planeR) : P::czero();
+    const int cl = col < 0 ? 0 : (col >= n ? n - 1 : col);
+    return P::load(R + (size_t)cl * ldr + ic, planeR);
   };
-  // Rings of BP_RING columns in flight: slot t serves the columns
-  // top - t, top - t - BP_RING, ... (static register indices).
-  C rb[BP_RING];  // the block's own columns r1-1, r1-2, ...
+  auto xload = [&](int col) __attribute__((always_inline)) {
+    bool m = false;
+    const int cl = col < 0 ? 0 : (col >= n ? n - 1 : col);
+    return bs_coh_load<P>(x + cl, (size_t)n, m);
+  };
+  // The block's own columns r1-1, r1-2, ... in a ring (slot t: r1-1-t-8k).
+  C rb[BP_RING];
 #pragma unroll
-  for (int t = 0; t < BP_RING; ++t) rb[t] = r1 - 1 - t > r0 ? rload(r1 - 1 - t) : P::czero();
-  // 1. Columns above the block, descending, each once x_c is out; R and x
-  // loaded BP_RING columns ahead.
+  for (int t = 0; t < BP_RING; ++t) rb[t] = rload(r1 - 1 - t);
+  // 1. Columns above the block, descending, in chunks of CH columns: the R
+  // entries and x values of the next chunk are loaded while the current
+  // one is applied (two buffers, so no register moves between chunks); a
+  // chunk is applied once all its x are out (at the front they arrive one
+  // at a time: the chunk's x are reloaded until they are).
   const long long t0 = wall_clock64();
   {
-    C ra[BP_RING], xa[BP_RING];
+    constexpr int CH = P::L == 4 ? 4 : 8;
+    C ra0[CH], xa0[CH], ra1[CH], xa1[CH];
+    auto fetch = [&](int c0, C (&rr)[CH], C (&xx)[CH]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int t = 0; t < BP_RING; ++t) {
-      const int col = n - 1 - t;
-      bool miss = false;
-      ra[t] = col >= r1 ? rload(col) : P::czero();
-      xa[t] = col >= r1 ? bs_coh_load<P>(x + col, (size_t)n, miss) : P::czero();
-    }
-    int c = n - 1;
-    while (c >= r1) {
+      for (int u = 0; u < CH; ++u) {
+        rr[u] = rload(c0 - u);
+        xx[u] = xload(c0 - u);
+      }
+    };
+    // false on time-out
+    auto ready = [&](int c0, C (&xx)[CH]) __attribute__((always_inline)) {
+      while (true) {
+        bool miss = false;
 #pragma unroll
-      for (int t = 0; t < BP_RING; ++t) {
-        if (c >= r1) {
-          while (true) {  // x_c, unless the early load already saw it
-            bool miss = false;
-            const double *pv = reinterpret_cast<const double *>(&xa[t]);
-#pragma unroll
-            for (int q = 0; q < 2 * P::L; ++q) miss = miss || __double_as_longlong(pv[q]) == RES_EMPTY;
-            if (__ballot(miss) == 0) break;
-            if (wall_clock64() - t0 > spin_ticks) {
-              if (lane == 0 && info != nullptr)
-                __hip_atomic_store(info, MGS_INFO_SYNC_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              return;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            bool m2 = false;
-            xa[t] = bs_coh_load<P>(x + c, (size_t)n, m2);
-          }
-          if (mine) P::upd(yv, ra[t], xa[t]);
-          const int cn = c - BP_RING;
-          if (cn >= r1) {
-            bool m3 = false;
-            ra[t] = rload(cn);
-            xa[t] = bs_coh_load<P>(x + cn, (size_t)n, m3);
-          }
-          --c;
+        for (int u = 0; u < CH; ++u) miss = miss || (c0 - u >= r1 && bs_empty<P>(xx[u]));
+        if (__ballot(miss) == 0) return true;
+        if (wall_clock64() - t0 > spin_ticks) {
+          if (lane == 0 && info != nullptr)
+            __hip_atomic_store(info, MGS_INFO_SYNC_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          return false;
         }
+        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int u = 0; u < CH; ++u) xx[u] = xload(c0 - u);
       }
+    };
+    auto apply = [&](int c0, const C (&rr)[CH], const C (&xx)[CH]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        C yn = yv;
+        P::upd(yn, rr[u], xx[u]);
+        yv = bs_pick<P>(mine && c0 - u >= r1, yn, yv);
+      }
+    };
+    const int nch = (n - r1 + CH - 1) / CH;
+    int c = n - 1;
+    fetch(c, ra0, xa0);
+#pragma unroll 1
+    for (int k = 0; k < nch; k += 2) {
+      fetch(c - CH, ra1, xa1);
+      if (!ready(c, xa0)) return;
+      apply(c, ra0, xa0);
+      c -= CH;
+      if (k + 1 >= nch) break;
+      fetch(c - CH, ra0, xa0);
+      if (!ready(c, xa1)) return;
+      apply(c, ra1, xa1);
+      c -= CH;
     }
   }
-  // 2. The block itself: x_c from its lane, broadcast, published, applied
-  // to the rows above it (R from the ring, BP_RING columns ahead).
+#ifdef MGS_TRACE
+  if (trace != nullptr && lane == 0) trace[blockIdx.x * 4 + 1] = (long long)wall_clock64();
+#endif
+  // 2. The block itself: x_c from its lane, broadcast, applied to the rows
+  // above it (R from the ring, BP_RING columns ahead).  Each lane keeps its
+  // own x (the empty marker until solved) and every step all lanes store
+  // theirs, so x_c is out one step after it is formed, with no branch.
+  C xown;
+  {
+    double *po = reinterpret_cast<double *>(&xown);
+#pragma unroll
+    for (int q = 0; q < 2 * P::L; ++q) po[q] = __longlong_as_double(RES_EMPTY);
+  }
+  const int rounds2 = (r1 - r0 + BP_RING - 1) / BP_RING;
   int cc = r1 - 1;
-  while (cc >= r0) {
+#pragma unroll 1
+  for (int rd = 0; rd < rounds2; ++rd) {
 #pragma unroll
     for (int t = 0; t < BP_RING; ++t) {
-      if (cc >= r0) {
-        const C xk = bs_readlane<P>(P::scale(yv, inv), cc - r0);
-        if (lane == cc - r0) bs_coh_store<P>(x + cc, (size_t)n, xk);
-        if (lane < cc - r0) P::upd(yv, rb[t], xk);
-        const int cn = cc - BP_RING;
-        if (cn > r0) rb[t] = rload(cn);
-        --cc;
-      }
+      const int k = cc - r0;  // lane of row cc (negative past the block)
+      const C xk = bs_readlane<P>(P::scale(yv, inv), k & 63);
+      xown = bs_pick<P>(lane == k, xk, xown);
+      C yn = yv;
+      P::upd(yn, rb[t], xk);
+      yv = bs_pick<P>(lane < k, yn, yv);
+      if (mine) bs_coh_store<P>(x + i, (size_t)n, xown);
+      rb[t] = rload(cc - BP_RING);
+      --cc;
     }
   }
+#ifdef MGS_TRACE
+  if (trace != nullptr && lane == 0) trace[blockIdx.x * 4 + 2] = (long long)wall_clock64();
+#endif
 }
 
 }  // namespace mgsq

@@ -144,6 +144,12 @@ int dispatch_shape(const StepArgs &a, const Shape &sh, hipStream_t st) {
   return MGS_ERR_DIMS;
 }
 
+#ifdef MGS_TRACE
+// Diagnostic builds: stamps of the back substitution across workgroups
+// (4 per workgroup), set by mgs_set_trace_backsolve.
+long long *g_trace_bs = nullptr;
+#endif
+
 struct DevInfo {
   int cus;  // compute units when cooperative launches are supported, else 0
   long long wclk_khz;
@@ -170,7 +176,12 @@ int backsolve_pipe_launch(int n, const double *R, int ldr, size_t planeR, const 
   hipLaunchKernelGGL((bs_mark_kernel<P::L>), dim3(ceil_div(n, 256)), dim3(256), 0, st, n, x, info, skip);
   if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
   long long spin = d.wclk_khz * 2000;  // 2 s
-  void *args[] = {&n, &R, &ldr, &planeR, &y, &planeY, &x, &info, &skip, &spin};
+#ifdef MGS_TRACE
+  long long *trace = g_trace_bs;
+#else
+  long long *trace = nullptr;
+#endif
+  void *args[] = {&n, &R, &ldr, &planeR, &y, &planeY, &x, &info, &skip, &spin, &trace};
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G), dim3(BP_ROWS), args, 0, st) !=
       hipSuccess) {
     (void)hipGetLastError();
@@ -431,7 +442,7 @@ int res_max_cols(int ncols, int bw, int G) {
   for (int g = 0; g < G; ++g) {
     int cnt = 0;
     for (int i = 0;; ++i) {
-      const int qi = 2 * G * (i / 2) + ((i & 1) ? 2 * G - 1 - g : g);
+      const int qi = res_position(i, g, G);
       if (qi >= np) break;
       const int p = np - 1 - qi;
       cnt += (ncols - p * bw < bw) ? ncols - p * bw : bw;
@@ -640,6 +651,7 @@ extern "C" {
 #ifdef MGS_TRACE
 // Diagnostic builds only (not declared in the public header).
 void mgs_set_trace(long long *buf) { g_trace = buf; }
+void mgs_set_trace_backsolve(long long *buf) { g_trace_bs = buf; }
 #endif
 
 int mgs_abi_version(void) { return MGS_ABI_VERSION; }

@@ -13,7 +13,9 @@
 //    are block sums over the workgroup.  Columns are dealt to the G
 //    workgroups in a reflected cyclic order counted from the last column
 //    (workgroup g gets np-1-g, np-1-(2G-1-g), np-1-(2G+g), ...), so that
-//    every workgroup owns about the same triangular amount of work.
+//    every workgroup owns about the same triangular amount of work; near
+//    the reflection points neighbours trade places so that no workgroup
+//    owns two columns close together (res_position).
 //  * Bulk projections (apply) sum the inner products of all of a
 //    workgroup's columns at once: partials through LDS, one wave per
 //    column reduces, a second barrier shares the result.  They read q_k
@@ -92,6 +94,35 @@ constexpr int RES_TRACE_SLOTS = 8;
 
 // Sentinel column index of an empty slot.
 constexpr int RES_NONE = 1 << 30;
+
+// Position (counted from the last panel) of the i-th panel of workgroup g
+// among G: the reflected cyclic order g, 2G-1-g, 2G+g, 4G-1-g, ..., which
+// balances the triangular work, except near the reflection points, where
+// that order gives a workgroup two panels 2g+1 (odd blocks, g small) or
+// 2G-1-2g (even blocks, g near G) apart: there the workgroup trades its
+// place in that block with the one 2 RES_SEP away, so that no workgroup
+// owns two panels fewer than 2 RES_SEP + 1 apart (its second panel would
+// otherwise wait for the projections it deferred to favour the first).  The
+// trade moves 2 RES_SEP positions per block: the balance changes by a few
+// percent.  Shared by the kernel and the host (same arithmetic).
+constexpr int RES_SEP = 25;
+__host__ __device__ __forceinline__ int res_position(int i, int g, int G) {
+  int gg = g;
+  if (G >= 6 * RES_SEP) {
+    if (i & 1) {
+      if (g < RES_SEP)
+        gg = g + 2 * RES_SEP;
+      else if (g >= 2 * RES_SEP && g < 3 * RES_SEP)
+        gg = g - 2 * RES_SEP;
+    } else {
+      if (g >= G - RES_SEP)
+        gg = g - 2 * RES_SEP;
+      else if (g >= G - 3 * RES_SEP && g < G - 2 * RES_SEP)
+        gg = g + 2 * RES_SEP;
+    }
+  }
+  return 2 * G * (i / 2) + ((i & 1) ? 2 * G - 1 - gg : gg);
+}
 
 // Synchronisation words: wave w's counter at 16 w (w < 16, one 64-byte
 // line each), the arrival count of the start barrier and the abort flag in
@@ -581,7 +612,7 @@ struct Resident {
       return;
     }
     const int u = nq - 1 - i;
-    const int qi = 2 * a.G * (u / 2) + ((u & 1) ? 2 * a.G - 1 - g : g);
+    const int qi = res_position(u, g, a.G);
     ps = (a.np - 1 - qi) * a.bw;
     pe = ps + a.bw < a.ncols ? ps + a.bw : a.ncols;
   }
@@ -594,11 +625,11 @@ struct Resident {
     const int bid = blockIdx.x;
     const int G = a.G;
     const int g = a.xcd_group ? (bid % 8) * a.xcd_group + bid / 8 : bid;
-    // Owned panels: the i-th is q_i = 2G*(i/2) + (i even ? g : 2G-1-g) in
-    // reflected order, panel np-1-q_i; ascending columns = descending i.
+    // Owned panels: the i-th is q_i = res_position(i, g, G) (reflected
+    // order), panel np-1-q_i; ascending columns = descending i.
     int nq = 0;
     while (true) {
-      const int qi = 2 * G * (nq / 2) + ((nq & 1) ? 2 * G - 1 - g : g);
+      const int qi = res_position(nq, g, G);
       if (qi >= a.np) break;
       ++nq;
     }
