@@ -15,7 +15,9 @@ and quad-double arithmetic, of what the paper defines:
 * the closed-form adjoint (dL/dA, dL/db) of the least-squares solution for
   L = Re(g^H x) (the differentiation form; not in the paper),
 * the precision form (not in the paper): FP64 blocked MGS, then iterative
-  refinement with the residual in quad-double.
+  refinement with the residual in quad-double,
+* a polynomial system's values and Jacobian, and Newton's method with the
+  MGS least-squares solve (Section 7: the corrector of a path tracker).
 
 Array layout ("planar"): a complex matrix with ``cols`` columns and leading
 dimension ``ld`` in L-limb precision is a float64 array of shape
@@ -74,8 +76,10 @@ def lib():
         L.orc_adjoint.argtypes = [I, I, I, P, I, P, P, P, P, P, I]
         L.orc_emax_batch.argtypes = [I, I, I, I, P, I, P, I, P, I, P, I]
         L.orc_refine.argtypes = [I, I, I, P, I, P, P, P, I, ctypes.c_double, I, P, P, I]
+        L.orc_poly_eval.argtypes = [I, I, I, I, I, P, P, P, P, P, P]
+        L.orc_newton.argtypes = [I, I, I, I, I, P, P, P, P, I, P]
         for f in (L.orc_mgs, L.orc_backsolve, L.orc_ls_solve, L.orc_arith, L.orc_errors, L.orc_adjoint,
-                  L.orc_emax_batch, L.orc_refine):
+                  L.orc_emax_batch, L.orc_refine, L.orc_poly_eval, L.orc_newton):
             f.restype = I
         _lib = L
     return _lib
@@ -201,6 +205,41 @@ def refine(A, b, block=64, tol=None, max_iter=30, nthreads=0):
     if info < -2:
         raise ValueError("orc_refine argument error %d" % info)
     return dict(x=x, x0=x0, iters=it.value, err_est=est.value, info=info)
+
+
+def _sys(system):
+    v = np.ascontiguousarray(system["vars"], dtype=np.int32)
+    d = np.ascontiguousarray(system["exps"], dtype=np.int32)
+    c = _c(system["coef"])
+    neq, nmon, nvpm = v.shape
+    return v, d, c, neq, nmon, nvpm, int(system["nvar"])
+
+
+def poly_eval(system, x):
+    """F = f(x) (L,2,neq) and the Jacobian J (L,2,nvar,neq) of a polynomial
+    system: dict(vars, exps [neq,nmon,nvpm], coef (L,2,neq,nmon), nvar)."""
+    v, d, c, neq, nmon, nvpm, nvar = _sys(system)
+    x = _c(x)
+    L = x.shape[0]
+    F = np.zeros((L, 2, neq))
+    J = np.zeros((L, 2, nvar, neq))
+    rc = lib().orc_poly_eval(L, neq, nvar, nmon, nvpm, _p(v), _p(d), _p(c), _p(x), _p(F), _p(J))
+    if rc != 0:
+        raise ValueError("orc_poly_eval error %d" % rc)
+    return F, J
+
+
+def newton(system, x0, iters):
+    """`iters` Newton steps from x0 with the MGS least-squares solve of
+    J d = -F; returns (x, correction norms)."""
+    v, d, c, neq, nmon, nvpm, nvar = _sys(system)
+    x = _c(x0).copy()
+    L = x.shape[0]
+    dn = np.zeros(max(iters, 1))
+    rc = lib().orc_newton(L, neq, nvar, nmon, nvpm, _p(v), _p(d), _p(c), _p(x), int(iters), _p(dn))
+    if rc != 0:
+        raise ValueError("orc_newton error %d" % rc)
+    return x, dn[:iters]
 
 
 def adjoint(A, b, g, nthreads=0):

@@ -11,6 +11,8 @@
 //   * Back substitution, Section 6, Figure 3: column oriented, for k = n..1:
 //     x_k = y_k / r_kk, then y_j -= r_jk x_k for j < k.
 //   * The accuracy measure of Section 4, Equation (2).
+//   * A polynomial system's values and Jacobian and Newton's method with the
+//     MGS least-squares solve (Section 7: the corrector of a path tracker).
 //   * The adjoint of the least-squares solution (not in the paper; the
 //     differentiation form built around it): for L = Re(g^H x) with
 //     x = argmin ||b - A x||, full column rank, r = b - A x and
@@ -337,6 +339,83 @@ void run_errors(int m, int n, const double *A, int lda, const double *Q, int ldq
   }
 }
 
+// Polynomial system (Section 7: the Newton corrector of a path tracker; the
+// workload of the paper's Table 6): equation e is
+//   f_e(x) = sum_m c_em prod_t x_{v_emt}^{d_emt},
+// t over the `nvpm` variables of monomial m.  F = f(x) (neq planar) and the
+// Jacobian J (neq x nvar planar, column j = d f / d x_j), every monomial and
+// derivative formed as written (powers by repeated products, the other
+// factors multiplied in t order), sums over m ascending.
+template <class T>
+void run_poly_eval(int neq, int nvar, int nmon, int nvpm, const int *vars, const int *exps, const double *coef,
+                   const double *x, double *F, double *J) {
+  CV<T> cv, xv;
+  read_planar<T>(coef, nmon, neq, nmon, cv);  // cv[e * nmon + m]
+  read_planar<T>(x, nvar, 1, nvar, xv);
+  CV<T> Fv(neq, czero<T>()), Jv((size_t)neq * nvar, czero<T>());  // Jv[j * neq + e]
+  const C<T> one = {Limbs<T>::from(1.0), Limbs<T>::from(0.0)};
+  auto power = [&](const C<T> &b, int d) {
+    C<T> r = one;
+    for (int k = 0; k < d; ++k) r = cmul(r, b);
+    return r;
+  };
+  for (int e = 0; e < neq; ++e) {
+    for (int m = 0; m < nmon; ++m) {
+      const int *vm = vars + ((size_t)e * nmon + m) * nvpm;
+      const int *dm = exps + ((size_t)e * nmon + m) * nvpm;
+      const C<T> c = cv[(size_t)e * nmon + m];
+      C<T> mono = c;
+      for (int t = 0; t < nvpm; ++t) mono = cmul(mono, power(xv[vm[t]], dm[t]));
+      Fv[e] = cadd(Fv[e], mono);
+      for (int t = 0; t < nvpm; ++t) {
+        C<T> dv = cmul(c, {Limbs<T>::from((double)dm[t]), Limbs<T>::from(0.0)});
+        for (int u = 0; u < nvpm; ++u)
+          dv = cmul(dv, u == t ? power(xv[vm[u]], dm[u] - 1) : power(xv[vm[u]], dm[u]));
+        C<T> &dst = Jv[(size_t)vm[t] * neq + e];
+        dst = cadd(dst, dv);
+      }
+    }
+  }
+  write_planar<T>(F, neq, 1, neq, Fv);
+  write_planar<T>(J, neq, nvar, neq, Jv);
+}
+
+// Newton's method on the system: K steps of x <- x + d, d the least-squares
+// solution of J(x) d = -F(x) by MGS on [J -F] (Figure 1, Equation (1)) and
+// back substitution (Figure 3).  x (nvar planar) is updated in place;
+// dnorm[k] = FP64 2-norm of the k-th correction.  Returns 0 or the info of
+// a failed factorisation.
+template <class T>
+int run_newton(int neq, int nvar, int nmon, int nvpm, const int *vars, const int *exps, const double *coef,
+               double *x, int iters, double *dnorm) {
+  const int L = Limbs<T>::L;
+  std::vector<double> F((size_t)2 * L * neq), J((size_t)2 * L * neq * nvar);
+  for (int k = 0; k < iters; ++k) {
+    run_poly_eval<T>(neq, nvar, nmon, nvpm, vars, exps, coef, x, F.data(), J.data());
+    for (double &v : F) v = -v;
+    CV<T> W;
+    read_planar<T>(J.data(), neq, nvar, neq, W);
+    CV<T> bb;
+    read_planar<T>(F.data(), neq, 1, neq, bb);
+    W.insert(W.end(), bb.begin(), bb.end());
+    CV<T> Rv;
+    const int info = mgs<T>(neq, nvar, nvar + 1, W, Rv, 1);
+    if (info != 0) return info;
+    CV<T> y(Rv.begin() + (size_t)nvar * nvar, Rv.begin() + (size_t)nvar * nvar + nvar), d(nvar);
+    backsolve<T>(nvar, Rv.data(), nvar, y, d.data());
+    CV<T> xv;
+    read_planar<T>(x, nvar, 1, nvar, xv);
+    double s = 0.0;
+    for (int j = 0; j < nvar; ++j) {
+      xv[j] = cadd(xv[j], d[j]);
+      s += hi(d[j].re) * hi(d[j].re) + hi(d[j].im) * hi(d[j].im);
+    }
+    write_planar<T>(x, nvar, 1, nvar, xv);
+    if (dnorm) dnorm[k] = std::sqrt(s);
+  }
+  return 0;
+}
+
 int threads_or_default(int t) { return t > 0 ? t : omp_get_max_threads(); }
 
 // ------------------------------------------------------ precision form ----
@@ -577,6 +656,38 @@ int orc_emax_batch(int prec, int count, int m, int n, const double *A, int lda, 
     out[s] = o[0];
   }
   return 0;
+}
+
+// F = f(x) and the Jacobian J of the polynomial system (see run_poly_eval):
+// vars, exps [neq][nmon][nvpm]; coef planar (prec, 2, neq, nmon): monomial
+// m of equation e at e * nmon + m; x planar (prec, 2, nvar); F planar (prec,
+// 2, neq); J planar (prec, 2, nvar, neq).
+int orc_poly_eval(int prec, int neq, int nvar, int nmon, int nvpm, const int *vars, const int *exps,
+                  const double *coef, const double *x, double *F, double *J) {
+  if (neq < 1 || nvar < 1 || nmon < 1 || nvpm < 1) return -1;
+  for (size_t k = 0; k < (size_t)neq * nmon * nvpm; ++k)
+    if (vars[k] < 0 || vars[k] >= nvar || exps[k] < 0) return -2;
+  switch (prec) {
+    case 1: run_poly_eval<double>(neq, nvar, nmon, nvpm, vars, exps, coef, x, F, J); return 0;
+    case 2: run_poly_eval<DD>(neq, nvar, nmon, nvpm, vars, exps, coef, x, F, J); return 0;
+    case 4: run_poly_eval<QD>(neq, nvar, nmon, nvpm, vars, exps, coef, x, F, J); return 0;
+  }
+  return -3;
+}
+
+// `iters` Newton steps on the polynomial system from x (updated in place);
+// dnorm (iters doubles or NULL) receives the norms of the corrections.
+int orc_newton(int prec, int neq, int nvar, int nmon, int nvpm, const int *vars, const int *exps,
+               const double *coef, double *x, int iters, double *dnorm) {
+  if (neq < nvar || nvar < 1 || nmon < 1 || nvpm < 1 || iters < 0) return -1;
+  for (size_t k = 0; k < (size_t)neq * nmon * nvpm; ++k)
+    if (vars[k] < 0 || vars[k] >= nvar || exps[k] < 0) return -2;
+  switch (prec) {
+    case 1: return run_newton<double>(neq, nvar, nmon, nvpm, vars, exps, coef, x, iters, dnorm);
+    case 2: return run_newton<DD>(neq, nvar, nmon, nvpm, vars, exps, coef, x, iters, dnorm);
+    case 4: return run_newton<QD>(neq, nvar, nmon, nvpm, vars, exps, coef, x, iters, dnorm);
+  }
+  return -3;
 }
 
 }  // extern "C"

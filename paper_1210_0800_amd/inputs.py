@@ -332,6 +332,51 @@ def config5():
     return dict(A=A, b=b, g=gx, prec=2, m=m, n=n)
 
 
+def polysys(neq=32, nvar=32, nmon=32, nvpm=5, maxdeg=5, L=2, system=0):
+    """Polynomial system of the paper's Table 6 shape (Section 7: Newton
+    corrector; 32 equations in 32 variables, 32 monomials per equation, 5
+    distinct variables per monomial, degrees uniform in 1..maxdeg), with a
+    known root x* whose entries are 1, -1, i or -i (role 6).
+
+    Coefficients are dyadic complex numbers k/64, |k| <= 64 (role 0); the
+    first monomial's coefficient of each equation is then set to
+    -sum_{m>0} c_m mono_m(x*) / mono_0(x*), exact in FP64 since every
+    monomial value at x* is a power of i.  So f(x*) = 0 exactly.  Returns
+    dict(vars, exps [neq, nmon, nvpm] int32, coef (L, 2, neq, nmon), nvar,
+    root (L, 2, nvar))."""
+    g = rng(6, system, 0)
+    vars_ = np.zeros((neq, nmon, nvpm), dtype=np.int32)
+    exps = g.integers(1, maxdeg + 1, size=(neq, nmon, nvpm)).astype(np.int32)
+    for e in range(neq):
+        for m in range(nmon):
+            vars_[e, m] = g.choice(nvar, nvpm, replace=False)
+    cre = g.integers(-64, 65, size=(neq, nmon)) / 64.0
+    cim = g.integers(-64, 65, size=(neq, nmon)) / 64.0
+    rg = rng(6, system, 6)
+    root_pow = rg.integers(0, 4, size=nvar)  # x*_j = i^root_pow[j]
+    units = [1, 1j, -1, -1j]
+    coef = cre + 1j * cim
+    for e in range(neq):
+        vals = [units[int(np.sum(exps[e, m] * root_pow[vars_[e, m]])) % 4] for m in range(nmon)]
+        rest = sum(coef[e, m] * vals[m] for m in range(1, nmon))
+        coef[e, 0] = -rest / vals[0]
+    C = np.zeros((L, 2, neq, nmon))
+    C[0, 0], C[0, 1] = coef.real, coef.imag
+    root = np.zeros((L, 2, nvar))
+    rv = np.array([units[p] for p in root_pow])
+    root[0, 0], root[0, 1] = rv.real, rv.imag
+    return dict(vars=vars_, exps=exps, coef=C, nvar=nvar, root=root)
+
+
+def near_root(sys, scale=1e-3, L=2, system=0):
+    """A start point x* + delta, delta complex with entries scale * U[-1,1]
+    (role 7), as the predictor of a path tracker would hand the corrector."""
+    g = rng(6, system, 7)
+    x = np.zeros((L,) + sys["root"].shape[1:])
+    x[0] = sys["root"][0] + scale * g.uniform(-1.0, 1.0, sys["root"].shape[1:])
+    return x
+
+
 def random_problem(prec, m, n, seed=0, dist="uniform", config=0):
     """Generic seeded test problem: A (prec,2,n,m) and b (prec,2,m)."""
     A = random_complex(rng(config, seed, 0), (n, m), prec, dist)
