@@ -1,5 +1,6 @@
 // Back substitution of Section 6, Figure 3 spread over workgroups: for
-// k = n..1, x_k = y_k / r_kk, then y_j -= r_jk x_k for j < k.
+// k = n..1, x_k = y_k / r_kk, then y_j -= r_jk x_k for j < k (and its
+// mirror image, the forward substitution R^H w = g of the adjoint).
 //
 // Workgroup j is one wave holding rows [64j, 64j + 64) of y, one row per
 // lane.  It applies r_ic x_c to its rows for every column c above its
@@ -87,18 +88,26 @@ __device__ __forceinline__ typename P::C bs_pick(bool pick, const typename P::C 
   return r;
 }
 
+// The triangular solve across workgroups.  FWD = false: R x = y (back
+// substitution, Figure 3: columns descending, rows above the pivot
+// updated).  FWD = true: R^H x = y (the adjoint's forward substitution:
+// columns ascending, entry (i, c) of R^H is conj(r_ci), rows below the
+// pivot updated), with the same operations per row as the one-workgroup
+// blocked kernels.
+//
 // Memory operations in the loops below are unconditional (addresses
 // clamped into the arrays, unused values discarded by selects) and the loops
 // run whole rings, so that the compiler can count the loads in flight and
 // wait only for the one a step consumes.
-template <class P>
-__global__ __launch_bounds__(BP_ROWS) void backsolve_pipe_kernel(int n, const double *R, int ldr, size_t planeR,
-                                                                 const double *y, size_t planeY, double *x,
-                                                                 int *info, const int *skip, long long spin_ticks,
-                                                                 long long *trace) {
+template <class P, bool FWD>
+__global__ __launch_bounds__(BP_ROWS) void trsv_pipe_kernel(int n, const double *R, int ldr, size_t planeR,
+                                                            const double *y, size_t planeY, double *x, int *info,
+                                                            const int *skip, long long spin_ticks,
+                                                            long long *trace) {
   if (skip != nullptr && *skip != 0) return;
   using C = typename P::C;
   using Rl = typename P::R;
+  constexpr int DIR = FWD ? 1 : -1;  // column order
   const int lane = threadIdx.x;
   const int r0 = blockIdx.x * BP_ROWS;
 #ifdef MGS_TRACE
@@ -120,43 +129,67 @@ __global__ __launch_bounds__(BP_ROWS) void backsolve_pipe_kernel(int n, const do
     inv = P::rzero();
   }
   if (mine && !P::ok_norm(dg.re) && info != nullptr) info_first_bad(info, i + 1);
-  // R(i, col) for this lane's row; col clamped into [0, n).
+  // Entry (row i, column col) of the triangular matrix; col clamped.
   auto rload = [&](int col) __attribute__((always_inline)) {
     const int cl = col < 0 ? 0 : (col >= n ? n - 1 : col);
-    return P::load(R + (size_t)cl * ldr + ic, planeR);
+    if constexpr (FWD)
+      return P::conj(P::load(R + (size_t)ic * ldr + cl, planeR));
+    else
+      return P::load(R + (size_t)cl * ldr + ic, planeR);
   };
   auto xload = [&](int col) __attribute__((always_inline)) {
     bool m = false;
     const int cl = col < 0 ? 0 : (col >= n ? n - 1 : col);
     return bs_coh_load<P>(x + cl, (size_t)n, m);
   };
-  // The block's own columns r1-1, r1-2, ... in a ring (slot t: r1-1-t-8k).
+  // The block's own columns in solve order in a ring (slot t: the t-th,
+  // (t+8)-th, ... column).
+  const int c2 = FWD ? r0 : r1 - 1;
   C rb[BP_RING];
 #pragma unroll
-  for (int t = 0; t < BP_RING; ++t) rb[t] = rload(r1 - 1 - t);
-  // 1. Columns above the block, descending, in chunks of CH columns: the R
-  // entries and x values of the next chunk are loaded while the current
-  // one is applied (two buffers, so no register moves between chunks); a
-  // chunk is applied once all its x are out (at the front they arrive one
-  // at a time: the chunk's x are reloaded until they are).
+  for (int t = 0; t < BP_RING; ++t) rb[t] = rload(c2 + DIR * t);
+  // 1. The columns solved before the block (above it for R x = y, left of
+  // it for R^H x = y), in solve order, in chunks of CH columns: the entries
+  // and x values of the next chunk are loaded while the current one is
+  // applied (two buffers, so no register moves between chunks); at the
+  // front, where x arrives one entry at a time, each entry is applied as it
+  // comes.
   const long long t0 = wall_clock64();
   {
     constexpr int CH = P::L == 4 ? 4 : 8;
+    const int ncol = FWD ? r0 : n - r1;  // columns of phase 1
+    const int c1 = FWD ? 0 : n - 1;      // the first of them
     C ra0[CH], xa0[CH], ra1[CH], xa1[CH];
-    auto fetch = [&](int c0, C (&rr)[CH], C (&xx)[CH]) __attribute__((always_inline)) {
+    auto fetch = [&](int s0, C (&rr)[CH], C (&xx)[CH]) __attribute__((always_inline)) {
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
-        rr[u] = rload(c0 - u);
-        xx[u] = xload(c0 - u);
+        rr[u] = rload(c1 + DIR * (s0 + u));
+        xx[u] = xload(c1 + DIR * (s0 + u));
       }
     };
-    // false on time-out
-    auto ready = [&](int c0, C (&xx)[CH]) __attribute__((always_inline)) {
+    // Applies the chunk starting at step s0, in order, each entry as soon
+    // as it (and every earlier one) is out: the entries already applied are
+    // kept by the selects, the rest reloaded while waiting.  False on
+    // time-out.
+    auto consume = [&](int s0, const C (&rr)[CH], C (&xx)[CH]) __attribute__((always_inline)) {
+      int done = 0;
       while (true) {
-        bool miss = false;
+        int avail = 0;
+        bool gap = false;
 #pragma unroll
-        for (int u = 0; u < CH; ++u) miss = miss || (c0 - u >= r1 && bs_empty<P>(xx[u]));
-        if (__ballot(miss) == 0) return true;
+        for (int u = 0; u < CH; ++u) {
+          const bool here = s0 + u >= ncol || __ballot(bs_empty<P>(xx[u])) == 0;
+          gap = gap || !here;
+          if (!gap) avail = u + 1;
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          C yn = yv;
+          P::upd(yn, rr[u], xx[u]);
+          yv = bs_pick<P>(mine && u >= done && u < avail && s0 + u < ncol, yn, yv);
+        }
+        done = avail;
+        if (done == CH) return true;
         if (wall_clock64() - t0 > spin_ticks) {
           if (lane == 0 && info != nullptr)
             __hip_atomic_store(info, MGS_INFO_SYNC_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -164,40 +197,30 @@ __global__ __launch_bounds__(BP_ROWS) void backsolve_pipe_kernel(int n, const do
         }
         __builtin_amdgcn_s_sleep(1);
 #pragma unroll
-        for (int u = 0; u < CH; ++u) xx[u] = xload(c0 - u);
+        for (int u = 0; u < CH; ++u) xx[u] = xload(c1 + DIR * (s0 + u));
       }
     };
-    auto apply = [&](int c0, const C (&rr)[CH], const C (&xx)[CH]) __attribute__((always_inline)) {
-#pragma unroll
-      for (int u = 0; u < CH; ++u) {
-        C yn = yv;
-        P::upd(yn, rr[u], xx[u]);
-        yv = bs_pick<P>(mine && c0 - u >= r1, yn, yv);
-      }
-    };
-    const int nch = (n - r1 + CH - 1) / CH;
-    int c = n - 1;
-    fetch(c, ra0, xa0);
+    const int nch = (ncol + CH - 1) / CH;
+    int s0 = 0;
+    fetch(s0, ra0, xa0);
 #pragma unroll 1
     for (int k = 0; k < nch; k += 2) {
-      fetch(c - CH, ra1, xa1);
-      if (!ready(c, xa0)) return;
-      apply(c, ra0, xa0);
-      c -= CH;
+      fetch(s0 + CH, ra1, xa1);
+      if (!consume(s0, ra0, xa0)) return;
+      s0 += CH;
       if (k + 1 >= nch) break;
-      fetch(c - CH, ra0, xa0);
-      if (!ready(c, xa1)) return;
-      apply(c, ra1, xa1);
-      c -= CH;
+      fetch(s0 + CH, ra0, xa0);
+      if (!consume(s0, ra1, xa1)) return;
+      s0 += CH;
     }
   }
 #ifdef MGS_TRACE
   if (trace != nullptr && lane == 0) trace[blockIdx.x * 4 + 1] = (long long)wall_clock64();
 #endif
   // 2. The block itself: x_c from its lane, broadcast, applied to the rows
-  // above it (R from the ring, BP_RING columns ahead).  Each lane keeps its
-  // own x (the empty marker until solved) and every step all lanes store
-  // theirs, so x_c is out one step after it is formed, with no branch.
+  // it reaches (R from the ring, BP_RING columns ahead).  Each lane keeps
+  // its own x (the empty marker until solved) and every step all lanes
+  // store theirs, so x_c is out one step after it is formed, with no branch.
   C xown;
   {
     double *po = reinterpret_cast<double *>(&xown);
@@ -205,20 +228,20 @@ __global__ __launch_bounds__(BP_ROWS) void backsolve_pipe_kernel(int n, const do
     for (int q = 0; q < 2 * P::L; ++q) po[q] = __longlong_as_double(RES_EMPTY);
   }
   const int rounds2 = (r1 - r0 + BP_RING - 1) / BP_RING;
-  int cc = r1 - 1;
+  int cc = c2;
 #pragma unroll 1
   for (int rd = 0; rd < rounds2; ++rd) {
 #pragma unroll
     for (int t = 0; t < BP_RING; ++t) {
-      const int k = cc - r0;  // lane of row cc (negative past the block)
+      const int k = cc - r0;  // lane of row cc (outside [0, 64) past the block)
       const C xk = bs_readlane<P>(P::scale(yv, inv), k & 63);
       xown = bs_pick<P>(lane == k, xk, xown);
       C yn = yv;
       P::upd(yn, rb[t], xk);
-      yv = bs_pick<P>(lane < k, yn, yv);
+      yv = bs_pick<P>(FWD ? lane > k : lane < k, yn, yv);
       if (mine) bs_coh_store<P>(x + i, (size_t)n, xown);
-      rb[t] = rload(cc - BP_RING);
-      --cc;
+      rb[t] = rload(cc + DIR * BP_RING);
+      cc += DIR;
     }
   }
 #ifdef MGS_TRACE

@@ -88,16 +88,6 @@ __device__ __forceinline__ typename P::Acc acc_lane63(const typename P::Acc &v) 
   }
   return r;
 }
-// r = sqrt(s) and 1 / r.
-template <class P>
-__device__ __forceinline__ void root_and_inverse(const typename P::R &s, typename P::R &root, typename P::R &inv) {
-  if constexpr (P::L == 2) {
-    P::sqrt_recip(s, root, inv);
-  } else {
-    root = P::sqrt_(s);
-    inv = P::recip(root);
-  }
-}
 
 template <class P, int NW, int CPW>
 __global__ __launch_bounds__(64 * NW) void mgs_batched_kernel(BatArgs a) {

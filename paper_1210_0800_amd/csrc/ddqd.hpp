@@ -217,6 +217,27 @@ __device__ __forceinline__ qd qd_sqrt(qd s) {
   return qd_add(x, {0.5 * h.x0, 0.5 * h.x1, 0.5 * h.x2, 0.5 * h.x3});
 }
 
+// sqrt(s) and 1/sqrt(s) together: the inverse square root y of qd_sqrt
+// (three Newton iterations from the FP64 one) is the reciprocal of the root
+// up to its last bits; one Newton step of the reciprocal from y,
+// y + y (1 - root y), takes it to full accuracy, in place of the three
+// iterations of qd_recip started from the FP64 reciprocal.
+__device__ __forceinline__ void qd_sqrt_recip(qd s, qd &root, qd &inv) {
+  qd y = qd_from(1.0 / sqrt(s.x0));
+  const qd one = qd_from(1.0);
+#pragma unroll 1
+  for (int it = 0; it < 3; ++it) {
+    qd r = qd_sub(one, qd_mul(s, qd_mul(y, y)));
+    qd h = qd_mul(y, r);
+    y = qd_add(y, {0.5 * h.x0, 0.5 * h.x1, 0.5 * h.x2, 0.5 * h.x3});
+  }
+  qd x = qd_mul(s, y);
+  qd d = qd_sub(s, qd_mul(x, x));
+  qd h = qd_mul(y, d);
+  root = qd_add(x, {0.5 * h.x0, 0.5 * h.x1, 0.5 * h.x2, 0.5 * h.x3});
+  inv = qd_add(y, qd_mul(y, qd_sub(one, qd_mul(root, y))));
+}
+
 // --------------------------------------------------------- precisions ----
 // A precision policy gathers what the kernels need: planar load / store,
 // accumulators for inner products and norms with their wave shuffles, the
@@ -247,6 +268,8 @@ struct PrecDD {
   }
   __device__ static __forceinline__ C czero() { return {{0.0, 0.0}, {0.0, 0.0}}; }
   __device__ static __forceinline__ R rzero() { return {0.0, 0.0}; }
+  __device__ static __forceinline__ R rfrom(double v) { return {v, 0.0}; }
+  __device__ static __forceinline__ R rone() { return {1.0, 0.0}; }
   __device__ static __forceinline__ void acc_zero(Acc &a) { a.sr = a.cr = a.si = a.ci = 0.0; }
 
   // acc += conj(q) * a
@@ -436,6 +459,8 @@ struct PrecQD {
     p[7 * plane] = v.im.x3;
   }
   __device__ static __forceinline__ R rzero() { return {0.0, 0.0, 0.0, 0.0}; }
+  __device__ static __forceinline__ R rfrom(double v) { return {v, 0.0, 0.0, 0.0}; }
+  __device__ static __forceinline__ R rone() { return {1.0, 0.0, 0.0, 0.0}; }
   __device__ static __forceinline__ C czero() { return {rzero(), rzero()}; }
   __device__ static __forceinline__ void acc_zero(Acc &a) { a = czero(); }
   __device__ static __forceinline__ void acc_cmulc(Acc &acc, const C &q, const C &a) {
@@ -481,6 +506,7 @@ struct PrecQD {
   __device__ static __forceinline__ C scale(const C &a, const R &s) { return {qd_mul(a.re, s), qd_mul(a.im, s)}; }
   __device__ static __forceinline__ R sqrt_(const R &s) { return qd_sqrt(s); }
   __device__ static __forceinline__ R recip(const R &s) { return qd_recip(s); }
+  __device__ static __forceinline__ void sqrt_recip(const R &s, R &root, R &inv) { qd_sqrt_recip(s, root, inv); }
   __device__ static __forceinline__ bool ok_norm(const R &s) {
     return s.x0 > 0.0 && s.x0 < INFINITY && fabs(s.x1) < INFINITY && fabs(s.x2) < INFINITY &&
            fabs(s.x3) < INFINITY;
@@ -512,6 +538,8 @@ struct PrecD {
   }
   __device__ static __forceinline__ C czero() { return {0.0, 0.0}; }
   __device__ static __forceinline__ R rzero() { return 0.0; }
+  __device__ static __forceinline__ R rfrom(double v) { return v; }
+  __device__ static __forceinline__ R rone() { return 1.0; }
   __device__ static __forceinline__ void acc_zero(Acc &a) { a.re = a.im = 0.0; }
   __device__ static __forceinline__ void acc_cmulc(Acc &acc, const C &q, const C &a) {
     acc.re = __fma_rn(q.re, a.re, acc.re);
@@ -559,5 +587,17 @@ struct PrecD {
   __device__ static __forceinline__ bool ok_norm(const R &s) { return s > 0.0 && s < INFINITY; }
   __device__ static __forceinline__ void store_real(double *p, size_t stride, const R &v) { p[0] = v; }
 };
+
+// r = sqrt(s) and 1 / r (dd and qd: the fused forms that share their
+// slow steps; FP64: the square root, then the division).
+template <class P>
+__device__ __forceinline__ void root_and_inverse(const typename P::R &s, typename P::R &root, typename P::R &inv) {
+  if constexpr (P::L >= 2) {
+    P::sqrt_recip(s, root, inv);
+  } else {
+    root = P::sqrt_(s);
+    inv = P::recip(root);
+  }
+}
 
 }  // namespace mgsq

@@ -263,8 +263,8 @@ __device__ __forceinline__ void panel_role(const StepArgs &a, typename P::Acc *l
       lds_barrier();
       typename P::R s2 = P::acc_value_re(s);
       if (!P::ok_norm(s2) && tid == 0 && *a.info == 0) *a.info = a.kbase + k + 1;
-      typename P::R rkk = P::sqrt_(s2);
-      typename P::R inv = P::recip(rkk);
+      typename P::R rkk, inv;
+      root_and_inverse<P>(s2, rkk, inv);
       size_t pq;
       double *dst = col_dst(a, k, pq);
 #pragma unroll

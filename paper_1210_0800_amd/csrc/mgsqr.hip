@@ -160,14 +160,14 @@ bool dev_info(DevInfo &d);
 // returns 1 when it does not apply (one block only, or the workgroups
 // cannot all be resident), so that the caller takes the one-workgroup
 // kernel.
-template <class P>
+template <class P, bool FWD = false>
 int backsolve_pipe_launch(int n, const double *R, int ldr, size_t planeR, const double *y, size_t planeY, double *x,
                           int *info, const int *skip, hipStream_t st) {
   if (n <= BP_ROWS) return 1;
   DevInfo d;
   if (!dev_info(d) || d.cus <= 0) return 1;
   const int G = ceil_div(n, BP_ROWS);
-  auto kern = backsolve_pipe_kernel<P>;
+  auto kern = trsv_pipe_kernel<P, FWD>;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), BP_ROWS, 0) !=
           hipSuccess ||
@@ -259,6 +259,8 @@ template <class P>
 int fwdsub_launch(int n, const double *R, int ldr, const double *g, double *w, int *info, hipStream_t st) {
   const int ny = pow2_at_least(ceil_div(n, BS_T));
   const size_t planeR = (size_t)ldr * n;
+  const int rc = backsolve_pipe_launch<P, true>(n, R, ldr, planeR, g, (size_t)n, w, info, nullptr, st);
+  if (rc != 1) return rc;
 #define MGS_FS_CASE(NYV)                                                                                       \
   case NYV:                                                                                                    \
     hipLaunchKernelGGL((fwdsub_blocked_kernel<P, NYV>), dim3(1), dim3(BS_T), 0, st, n, R, ldr, planeR, g, w, info); \
