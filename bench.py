@@ -341,6 +341,49 @@ def batched(torch, api, count=10000, reps=5):
     return out
 
 
+# The paper's Table 6, GPU column: seconds for 10,000 polynomial evaluations
+# and differentiations plus 10,000 MGS orthogonalisations of the 32 x 32
+# system (C2050; other hardware: context, not a target).
+PAPER_C2050_PE_MGS_S = {"d": 6.6, "dd": 18.6, "qd": 122.2}
+
+
+def newton_context(torch, api, steps=None, paths=1024, path_steps=5):
+    """The on-card Newton corrector on the Table 6 system shape (32
+    equations, 32 variables, 32 monomials of 5 variables, degrees 1..5):
+    one path, `steps` sequential Newton steps (evaluation, MGS on [J -f],
+    back substitution, update) in one mgs_newton_batched call; and `paths`
+    independent paths, `path_steps` steps each, in one call."""
+    from paper_1210_0800_amd import inputs
+
+    dev = torch.device("cuda:0")
+    steps = steps or {"d": 2000, "dd": 2000, "qd": 400}
+    out = {"protocol": "mgs_newton_batched on a seeded system with a known root, start 1e-3 from it; "
+                       "sequential: one path, steps back to back in one call; batched: %d paths x %d steps "
+                       "in one call" % (paths, path_steps),
+           "paper_hardware": "NVIDIA Tesla C2050; paper Table 6 (PE + MGS, GPU, per 10,000)"}
+    for prec, name in ((1, "d"), (2, "dd"), (4, "qd")):
+        s = inputs.polysys(L=prec, system=0)
+        sysd = api.PolySystem(s["vars"], s["exps"], s["coef"], s["nvar"], dev)
+        x0 = np.stack([inputs.near_root(s, 1e-3, L=prec, system=k) for k in range(paths)])
+        X1 = torch.from_numpy(x0[:1]).to(dev)
+        Xb = torch.from_numpy(x0).to(dev)
+        k = steps[name]
+        x = X1.clone()
+        r = api.newton_batched(sysd, x, k, dnorm=False)
+        torch.cuda.synchronize()
+        ok = int((r["info"] != 0).sum().item()) == 0
+        seq = _rate(torch, lambda: api.newton_batched(sysd, x, k, dnorm=False), 2, warm=1) * k
+        xb = Xb.clone()
+        bat = _rate(torch, lambda: api.newton_batched(sysd, xb, path_steps, dnorm=False), 3, warm=1)
+        bat *= paths * path_steps
+        paper = 10000 / PAPER_C2050_PE_MGS_S[name]
+        out[name] = {"sequential_steps_per_s": seq, "batched_point_steps_per_s": bat, "info_ok": ok,
+                     "paper_c2050_pe_mgs_per_s": paper, "sequential_ratio": seq / paper}
+        print("bench: newton %s: %.0f steps/s on one path, %.0f point-steps/s over %d paths (paper C2050 %.0f/s)"
+              % (name, seq, bat, paths, paper), file=sys.stderr, flush=True)
+    return out
+
+
 # FP64 flops of one qd 1024 x 1024 factorisation of [A b] (per-panel
 # schedule), counted by rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64
 # lanes, FMA = 2) over all step launches of one mgs_qr call; None until
@@ -411,6 +454,7 @@ def main():
     ap.add_argument("--only-context", action="store_true")
     ap.add_argument("--only-batched", action="store_true")
     ap.add_argument("--only-qd-large", action="store_true")
+    ap.add_argument("--only-newton", action="store_true")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -429,6 +473,13 @@ def main():
         from paper_1210_0800_amd import api
 
         print(json.dumps({"qd_1024x1024": qd_large(torch, api)}), flush=True)
+        return
+    if args.only_newton:
+        import torch
+
+        from paper_1210_0800_amd import api
+
+        print(json.dumps({"newton": newton_context(torch, api)}), flush=True)
         return
     if args.only_batched:
         import torch
@@ -544,6 +595,7 @@ def main():
         out["workloads"] = workloads(torch, api)
         out["batched"] = batched(torch, api)
         out["qd_1024x1024"] = qd_large(torch, api)
+        out["newton"] = newton_context(torch, api)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host[:4])
     print(json.dumps(out), flush=True)

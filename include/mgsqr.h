@@ -287,6 +287,65 @@ int mgs_lstsq_batched(int batch, int m, int n, int prec, const double *A, int ld
                       int ldq, double *R, int ldr, double *y, double *x, double *rho, int *info,
                       mgs_stream_t stream);
 
+/*
+ * Polynomial systems (Section 7: Newton's method as the corrector of a path
+ * tracker, the system defined once on the card, its evaluated Jacobian and
+ * values never leaving it; the workload of Table 6).  Equation e is
+ *   f_e(x) = sum_m c_em prod_t x_{v_emt}^{d_emt},
+ * m < nmon monomials of nvpm variables each.  Layouts:
+ *   vars, exps [in] device int32 [neq][nmon][nvpm]: variable index
+ *            (0 <= v < nvar) and exponent (0 <= d <= 16) of factor t of
+ *            monomial m of equation e (values outside are clamped into
+ *            those ranges).
+ *   coef [in] planar (prec, 2, neq, nmon): c_em at e*nmon + m, plane
+ *            stride neq*nmon.
+ *   x    points: batch vectors of nvar planar (point s at x + s*2*prec*nvar),
+ *            a torch view [batch, prec, 2, nvar].
+ * Limits: 1 <= nvar <= 63, 1 <= nmon <= 64, 1 <= nvpm <= 8, batch <= 65535.
+ */
+
+/*
+ * mgs_poly_eval -- F = f(x) and the Jacobian J = df/dx at batch points, in
+ * the working precision: monomials and their derivatives by products of
+ * powers, sums over the monomials in ascending order.
+ *   J [out] batch neq x nvar planar with leading dimension neq (column j =
+ *           d f / d x_j; point s at J + s*2*prec*neq*nvar), the A layout of
+ *           mgs_lstsq_batched.
+ *   F [out] batch vectors of neq (point s at F + s*2*prec*neq).
+ *   neq <= 65535.  No workspace.
+ */
+int mgs_poly_eval(int batch, int neq, int nvar, int nmon, int nvpm, int prec, const int *vars, const int *exps,
+                  const double *coef, const double *x, double *J, double *F, mgs_stream_t stream);
+
+/*
+ * mgs_newton_workspace_size -- bytes of device workspace mgs_newton_batched
+ * needs (J, -f, R and the correction of every point).
+ */
+int mgs_newton_workspace_size(int batch, int neq, int nvar, int prec, size_t *bytes);
+
+/*
+ * mgs_newton_batched -- `iters` Newton steps at each of batch points, all on
+ * the card: per step, f and J by mgs_poly_eval's kernel, the correction d
+ * as the least-squares solution of J d = -f by the MGS of Figure 1 on
+ * [J -f] (Equation (1)) and the back substitution of Figure 3 (the
+ * mgs_lstsq_batched kernel, one workgroup per point), then x += d.
+ *   Requires nvar <= neq <= 64 and 16 prec neq nvar <= 162816 (the MGS
+ *   limits of mgs_lstsq_batched), iters >= 0.
+ *   x     [in/out] the points (updated in place).
+ *   dnorm [out] iters x batch doubles or NULL: FP64 2-norm of the leading
+ *         limbs of step k's correction of point s at dnorm[k*batch + s];
+ *         NaN when that step's factorisation failed.
+ *   work  mgs_newton_workspace_size(batch, neq, nvar, prec) bytes.
+ *   info  [out] batch device ints: status of each point's last
+ *         factorisation (0, k > 0 for a zero or non-finite norm of column
+ *         k of J, MGS_INFO_SYNC_TIMEOUT); a failed point keeps its x for
+ *         that step.
+ * batch == 0 or iters == 0: nothing to do, pointers not examined.
+ */
+int mgs_newton_batched(int batch, int neq, int nvar, int nmon, int nvpm, int prec, const int *vars, const int *exps,
+                       const double *coef, double *x, int iters, double *dnorm, void *work, size_t work_bytes,
+                       int *info, mgs_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ MGS_MAX_ROWS = {1: 4096, 2: 4096, 4: 2048}
 
 EXPORTS = ("mgs_abi_version", "mgs_status_string", "mgs_workspace_size", "mgs_qr", "mgs_qr_schedule",
            "ls_solve", "ls_backsolve", "ls_adjoint", "mgs_refine_solve", "mgs_qr64", "mgs_lstsq_batched",
-           "mgs_qr_noalloc")
+           "mgs_qr_noalloc", "mgs_poly_eval", "mgs_newton_workspace_size", "mgs_newton_batched")
 SCHEDULES = {"auto": 0, "panel": 1, "resident": 2, "small": 3}
 
 _lib = None
@@ -65,6 +65,12 @@ def lib():
         L.mgs_lstsq_batched.restype = I
         L.mgs_qr_noalloc.argtypes = [I, I, I, P, I, P, I, P, I, P, P, P, P, P]
         L.mgs_qr_noalloc.restype = I
+        L.mgs_poly_eval.argtypes = [I, I, I, I, I, I, P, P, P, P, P, P, P]
+        L.mgs_poly_eval.restype = I
+        L.mgs_newton_workspace_size.argtypes = [I, I, I, I, ctypes.POINTER(S)]
+        L.mgs_newton_workspace_size.restype = I
+        L.mgs_newton_batched.argtypes = [I, I, I, I, I, I, P, P, P, P, I, P, P, S, P, P]
+        L.mgs_newton_batched.restype = I
         _lib = L
     return _lib
 
@@ -77,4 +83,10 @@ def check(fn, status):
 def workspace_size(m, n, prec, op):
     out = ctypes.c_size_t(0)
     check("mgs_workspace_size", lib().mgs_workspace_size(m, n, prec, op, ctypes.byref(out)))
+    return out.value
+
+
+def newton_workspace_size(batch, neq, nvar, prec):
+    out = ctypes.c_size_t(0)
+    check("mgs_newton_workspace_size", lib().mgs_newton_workspace_size(batch, neq, nvar, prec, ctypes.byref(out)))
     return out.value

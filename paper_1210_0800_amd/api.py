@@ -301,6 +301,75 @@ def lstsq_batched(A, b=None, *, Q=None, R=None, y=None, x=None, rho=None, info=N
     return dict(Q=Q, R=R, y=y, x=x, rho=rho, info=info)
 
 
+class PolySystem:
+    """A polynomial system on the card (Section 7: transferred once):
+    vars, exps int32 [neq, nmon, nvpm], coef float64 [prec, 2, neq, nmon]
+    (f_e = sum_m c_em prod_t x_{v_emt}^{d_emt}); nvar variables."""
+
+    def __init__(self, vars, exps, coef, nvar, device):
+        self.vars = torch.as_tensor(vars, dtype=torch.int32).contiguous().to(device)
+        self.exps = torch.as_tensor(exps, dtype=torch.int32).contiguous().to(device)
+        self.coef = torch.as_tensor(coef, dtype=torch.float64).contiguous().to(device)
+        if self.vars.dim() != 3 or self.exps.shape != self.vars.shape:
+            raise ValueError("vars and exps must both be [neq, nmon, nvpm]")
+        self.neq, self.nmon, self.nvpm = self.vars.shape
+        self.prec = self.coef.shape[0]
+        if tuple(self.coef.shape) != (self.prec, 2, self.neq, self.nmon):
+            raise ValueError("coef must be [prec, 2, neq, nmon], got %s" % (tuple(self.coef.shape),))
+        self.nvar = int(nvar)
+        self.device = self.coef.device
+
+    def _points(self, x):
+        if not isinstance(x, torch.Tensor) or x.dim() != 4 or x.dtype != torch.float64 or \
+                not x.is_contiguous() or x.device != self.device or \
+                tuple(x.shape[1:]) != (self.prec, 2, self.nvar):
+            raise ValueError("x must be a contiguous float64 [batch, %d, 2, %d] tensor on %s"
+                             % (self.prec, self.nvar, self.device))
+        return x.shape[0]
+
+
+def poly_eval(system, x, *, J=None, F=None):
+    """f(x) and the Jacobian at batch points x [batch, prec, 2, nvar]
+    (mgs_poly_eval).  Returns (J [batch, prec, 2, nvar, neq], F [batch,
+    prec, 2, neq])."""
+    batch = system._points(x)
+    shapeJ = (batch, system.prec, 2, system.nvar, system.neq)
+    shapeF = (batch, system.prec, 2, system.neq)
+    J = torch.empty(shapeJ, dtype=torch.float64, device=x.device) if J is None else J
+    F = torch.empty(shapeF, dtype=torch.float64, device=x.device) if F is None else F
+    for name, t, shp in (("J", J, shapeJ), ("F", F, shapeF)):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.device != x.device or tuple(t.shape) != shp:
+            raise ValueError("%s must be a contiguous float64 tensor of shape %s on %s" % (name, shp, x.device))
+    st = _lib.lib().mgs_poly_eval(batch, system.neq, system.nvar, system.nmon, system.nvpm, system.prec,
+                                  _ptr(system.vars), _ptr(system.exps), _ptr(system.coef), _ptr(x), _ptr(J),
+                                  _ptr(F), _stream(x))
+    _lib.check("mgs_poly_eval", st)
+    return J, F
+
+
+def newton_batched(system, x, iters, *, dnorm=True, info=None, work=None):
+    """`iters` Newton steps at each point of x [batch, prec, 2, nvar],
+    updated in place (mgs_newton_batched: evaluation, MGS on [J -f], back
+    substitution, update, all on the card).  Returns dict(x, dnorm [iters,
+    batch] or None, info [batch])."""
+    batch = system._points(x)
+    dev = x.device
+    nbytes = _lib.newton_workspace_size(batch, system.neq, system.nvar, system.prec)
+    work = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=dev) if work is None else work
+    _check_work(work, nbytes, dev)
+    info = torch.empty(max(batch, 1), dtype=torch.int32, device=dev) if info is None else info
+    if not isinstance(info, torch.Tensor) or info.dtype != torch.int32 or info.numel() < batch or \
+            info.device != dev or not info.is_contiguous():
+        raise ValueError("info must be a contiguous int32 tensor of >= %d entries on %s" % (batch, dev))
+    dn = torch.empty((max(iters, 1), max(batch, 1)), dtype=torch.float64, device=dev) if dnorm else None
+    st = _lib.lib().mgs_newton_batched(batch, system.neq, system.nvar, system.nmon, system.nvpm, system.prec,
+                                       _ptr(system.vars), _ptr(system.exps), _ptr(system.coef), _ptr(x),
+                                       int(iters), _ptr(dn), _ptr(work), work.numel() * work.element_size(),
+                                       _ptr(info), _stream(x))
+    _lib.check("mgs_newton_batched", st)
+    return dict(x=x, dnorm=None if dn is None else dn[:iters, :batch], info=info[:batch])
+
+
 class LstsqFn(torch.autograd.Function):
     """x = argmin ||b - A x|| by MGS on [A b] and back substitution, with the
     hand-written adjoint as its backward.

@@ -12,6 +12,7 @@
 #include "backsolve_kernels.hpp"
 #include "batched_kernels.hpp"
 #include "mgs_kernels.hpp"
+#include "newton_kernels.hpp"
 #include "precision_kernels.hpp"
 #include "resident_kernels.hpp"
 #include "small_kernels.hpp"
@@ -646,6 +647,66 @@ void *scratch_address() {
   return g_scratch_ptr[dev];
 }
 
+// Newton: J (batch systems of neq x nvar), b (batch x neq), R (batch x
+// nvar x nvar), d (batch x nvar), each in the working precision.
+struct NewtonWork {
+  double *A, *b, *R, *d;
+  size_t bytes;
+};
+NewtonWork newton_layout(int batch, int neq, int nvar, int prec, void *base) {
+  size_t off = 0;
+  auto take = [&](size_t nd) {
+    const size_t o = off;
+    off += round256(sizeof(double) * nd);
+    return reinterpret_cast<double *>(static_cast<char *>(base) + o);
+  };
+  const size_t NP = 2 * (size_t)prec, B = (size_t)batch;
+  NewtonWork w;
+  w.A = take(B * NP * neq * nvar);
+  w.b = take(B * NP * neq);
+  w.R = take(B * NP * nvar * nvar);
+  w.d = take(B * NP * nvar);
+  w.bytes = off;
+  return w;
+}
+bool newton_dims_ok(int batch, int neq, int nvar, int nmon, int nvpm, int prec) {
+  return batch >= 0 && batch <= 65535 && nvar >= 1 && nvar <= NT_MAX_VARS && neq >= nvar && nmon >= 1 && nmon <= NT_MAX_MON &&
+         nvpm >= 1 && nvpm <= NT_MAX_VPM && batched_fits(neq, nvar, nvar + 1, prec);
+}
+template <class P>
+int newton_launch(int batch, int neq, int nvar, int nmon, int nvpm, const int *vars, const int *exps,
+                  const double *coef, double *x, int iters, double *dnorm, const NewtonWork &w, int *info,
+                  long long spin, hipStream_t st) {
+  for (int k = 0; k < iters; ++k) {
+    hipLaunchKernelGGL((poly_eval_kernel<P>), dim3(neq, batch), dim3(64), 0, st, neq, nvar, nmon, nvpm, vars, exps,
+                       coef, x, w.A, w.b, true);
+    if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
+    BatArgs a;
+    a.batch = batch;
+    a.m = neq;
+    a.n = nvar;
+    a.ncols = nvar + 1;
+    a.A = w.A;
+    a.lda = neq;
+    a.b = w.b;
+    a.Q = w.A;  // in place
+    a.ldq = neq;
+    a.R = w.R;
+    a.ldr = nvar;
+    a.y = nullptr;
+    a.x = w.d;
+    a.rho = nullptr;
+    a.info = info;
+    a.spin_ticks = spin;
+    const int rc = batched_dispatch(P::L, a, st);
+    if (rc != MGS_OK) return rc;
+    hipLaunchKernelGGL((newton_update_kernel<P>), dim3(batch), dim3(64), 0, st, nvar, x, w.d, info,
+                       dnorm != nullptr ? dnorm + (size_t)k * batch : nullptr);
+    if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
+  }
+  return MGS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -865,6 +926,62 @@ int mgs_qr64(int m, int n, const double *A, int lda, const double *b, double *Q,
   hipLaunchKernelGGL(copy64_out_kernel, dim3(gx, n + 1), dim3(256), 0, st, m, n, w.Q64, w.R64, Q, ldq, R, ldr,
                      b != nullptr ? y : nullptr);
   return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
+}
+
+int mgs_poly_eval(int batch, int neq, int nvar, int nmon, int nvpm, int prec, const int *vars, const int *exps,
+                  const double *coef, const double *x, double *J, double *F, mgs_stream_t stream) {
+  if (!prec_ok(prec)) return MGS_ERR_PREC;
+  if (batch < 0 || neq < 1 || neq > 65535 || nvar < 1 || nvar > NT_MAX_VARS || nmon < 1 || nmon > NT_MAX_MON ||
+      nvpm < 1 || nvpm > NT_MAX_VPM || batch > 65535)
+    return MGS_ERR_DIMS;
+  if (batch == 0) return MGS_OK;
+  if (!aligned8(coef) || !aligned8(x) || !aligned8(J) || !aligned8(F)) return MGS_ERR_POINTER;
+  if (vars == nullptr || exps == nullptr || (reinterpret_cast<uintptr_t>(vars) & 3u) ||
+      (reinterpret_cast<uintptr_t>(exps) & 3u))
+    return MGS_ERR_POINTER;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (prec == 1)
+    hipLaunchKernelGGL((poly_eval_kernel<PrecD>), dim3(neq, batch), dim3(64), 0, st, neq, nvar, nmon, nvpm, vars,
+                       exps, coef, x, J, F, false);
+  else if (prec == 2)
+    hipLaunchKernelGGL((poly_eval_kernel<PrecDD>), dim3(neq, batch), dim3(64), 0, st, neq, nvar, nmon, nvpm, vars,
+                       exps, coef, x, J, F, false);
+  else
+    hipLaunchKernelGGL((poly_eval_kernel<PrecQD>), dim3(neq, batch), dim3(64), 0, st, neq, nvar, nmon, nvpm, vars,
+                       exps, coef, x, J, F, false);
+  return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
+}
+
+int mgs_newton_workspace_size(int batch, int neq, int nvar, int prec, size_t *bytes) {
+  if (!prec_ok(prec)) return MGS_ERR_PREC;
+  if (!newton_dims_ok(batch, neq, nvar, 1, 1, prec)) return MGS_ERR_DIMS;
+  if (bytes == nullptr) return MGS_ERR_POINTER;
+  *bytes = newton_layout(batch, neq, nvar, prec, nullptr).bytes;
+  return MGS_OK;
+}
+
+int mgs_newton_batched(int batch, int neq, int nvar, int nmon, int nvpm, int prec, const int *vars, const int *exps,
+                       const double *coef, double *x, int iters, double *dnorm, void *work, size_t work_bytes,
+                       int *info, mgs_stream_t stream) {
+  if (!prec_ok(prec)) return MGS_ERR_PREC;
+  if (!newton_dims_ok(batch, neq, nvar, nmon, nvpm, prec) || iters < 0) return MGS_ERR_DIMS;
+  if (batch == 0 || iters == 0) return MGS_OK;
+  if (!aligned8(coef) || !aligned8(x) || !aligned8(work) || !aligned8(info)) return MGS_ERR_POINTER;
+  if (vars == nullptr || exps == nullptr || (reinterpret_cast<uintptr_t>(vars) & 3u) ||
+      (reinterpret_cast<uintptr_t>(exps) & 3u))
+    return MGS_ERR_POINTER;
+  if (dnorm != nullptr && !aligned8(dnorm)) return MGS_ERR_POINTER;
+  const NewtonWork w = newton_layout(batch, neq, nvar, prec, work);
+  if (work_bytes < w.bytes) return MGS_ERR_WORKSPACE;
+  DevInfo d;
+  if (!dev_info(d)) return MGS_ERR_LAUNCH;
+  const long long spin = d.wclk_khz * 2000;  // 2 s
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (prec == 1)
+    return newton_launch<PrecD>(batch, neq, nvar, nmon, nvpm, vars, exps, coef, x, iters, dnorm, w, info, spin, st);
+  if (prec == 2)
+    return newton_launch<PrecDD>(batch, neq, nvar, nmon, nvpm, vars, exps, coef, x, iters, dnorm, w, info, spin, st);
+  return newton_launch<PrecQD>(batch, neq, nvar, nmon, nvpm, vars, exps, coef, x, iters, dnorm, w, info, spin, st);
 }
 
 int mgs_lstsq_batched(int batch, int m, int n, int prec, const double *A, int lda, const double *b, double *Q,

@@ -208,3 +208,45 @@ def test_mgs_lstsq_batched_rejects_bad_arguments():
     assert call(x=None) == -2                         # b given: y or x required
     assert call(y=FAKE + 16384) == -2                 # x aliases y
     assert call(Q=FAKE, ldq=33, m=32) in (-1, -2)
+
+
+def test_newton_workspace_and_refusals():
+    L = _lib.lib()
+    nb = ctypes.c_size_t(0)
+    # J, -f, R and the correction, each rounded up to 256 bytes
+    assert L.mgs_newton_workspace_size(3, 32, 32, 2, ctypes.byref(nb)) == 0
+    r256 = lambda v: (v + 255) // 256 * 256  # noqa: E731
+    assert nb.value == r256(3 * 4 * 32 * 32 * 8) + r256(3 * 4 * 32 * 8) + r256(3 * 4 * 32 * 32 * 8) + r256(3 * 4 * 32 * 8)
+    # more variables than equations, more than 64 equations, qd q vectors
+    # beyond LDS, too many variables, unsupported precision
+    for batch, neq, nvar, prec, st in ((1, 31, 32, 2, -1), (1, 65, 32, 2, -1), (1, 64, 63, 4, -1), (1, 64, 64, 2, -1),
+                                       (70000, 32, 32, 2, -1), (1, 32, 32, 3, -3)):
+        assert L.mgs_newton_workspace_size(batch, neq, nvar, prec, ctypes.byref(nb)) == st, (neq, nvar, prec)
+    P = ctypes.c_void_p(64)  # aligned, never dereferenced: refused before any launch
+    args = lambda batch, neq, nvar, nmon, nvpm, prec, iters: (  # noqa: E731
+        batch, neq, nvar, nmon, nvpm, prec, P, P, P, P, iters, None, P, 1 << 30, P, None)
+    assert L.mgs_newton_batched(*args(1, 32, 32, 65, 5, 2, 1)) == -1  # nmon > 64
+    assert L.mgs_newton_batched(*args(1, 32, 32, 32, 9, 2, 1)) == -1  # nvpm > 8
+    assert L.mgs_newton_batched(*args(1, 32, 32, 32, 5, 2, -1)) == -1
+    assert L.mgs_newton_batched(*args(1, 32, 33, 32, 5, 2, 1)) == -1
+    assert L.mgs_newton_batched(*args(0, 32, 32, 32, 5, 2, 1)) == 0  # nothing to do
+    assert L.mgs_newton_batched(*args(1, 32, 32, 32, 5, 2, 0)) == 0
+    a = list(args(1, 32, 32, 32, 5, 2, 1))
+    a[13] = 16  # workspace too small
+    assert L.mgs_newton_batched(*a) == -4
+    a = list(args(1, 32, 32, 32, 5, 2, 1))
+    a[6] = None  # vars
+    assert L.mgs_newton_batched(*a) == -2
+    a = list(args(1, 32, 32, 32, 5, 2, 1))
+    a[9] = ctypes.c_void_p(68)  # x misaligned
+    assert L.mgs_newton_batched(*a) == -2
+    # evaluation: bad sizes and pointers
+    ev = lambda batch, neq, nvar, nmon, nvpm, prec: (batch, neq, nvar, nmon, nvpm, prec, P, P, P, P, P, P, None)  # noqa: E731
+    assert L.mgs_poly_eval(*ev(1, 32, 64, 32, 5, 2)) == -1
+    assert L.mgs_poly_eval(*ev(1, 32, 32, 0, 5, 2)) == -1
+    assert L.mgs_poly_eval(*ev(-1, 32, 32, 32, 5, 2)) == -1
+    assert L.mgs_poly_eval(*ev(1, 32, 32, 32, 5, 5)) == -3
+    assert L.mgs_poly_eval(*ev(0, 32, 32, 32, 5, 2)) == 0
+    e = list(ev(1, 32, 32, 32, 5, 2))
+    e[10] = None  # J
+    assert L.mgs_poly_eval(*e) == -2

@@ -1,0 +1,175 @@
+"""GPU parity of the on-card Newton corrector (Section 7; the system shape of
+Table 6) through the C ABI (mgs_poly_eval, mgs_newton_batched), against
+the CPU oracle.
+
+* Evaluation: f and J at a batch of points, element by element against the
+  oracle, to a bound of a few thousand units of the working precision times
+  the size of the summed terms (the points stay near the unit circle, every
+  monomial is O(1)); at the constructed root f is exactly zero on both
+  sides.
+* Newton: after k steps from the same seeded start, the GPU iterate agrees
+  with the oracle's to the same bar times the conditioning of J (the MGS
+  solves differ by reduction order only), the correction norms agree, and
+  every point ends at the root to the precision floor.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1210_0800_amd import api, inputs  # noqa: E402
+from tests._exact import EPS  # noqa: E402
+from tests._parity import diff  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+# distance from the root after convergence: about 1e5 units of the precision
+FLOOR = {1: 1e-11, 2: 1e-27, 4: 1e-57}
+
+
+def T(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a)).to(torch.device(DEV))
+    return t if dtype is None else t.to(dtype)
+
+
+def _at(x, L):
+    y = np.zeros((L,) + x.shape[1:])
+    y[: min(L, x.shape[0])] = x[: min(L, x.shape[0])]
+    return y
+
+
+def make(L, **kw):
+    s = inputs.polysys(L=L, **kw)
+    s["coef"] = _at(s["coef"], L)
+    return s
+
+
+def dev_system(s):
+    return api.PolySystem(s["vars"], s["exps"], s["coef"], s["nvar"], torch.device(DEV))
+
+
+def starts(s, L, count, scale=1e-3):
+    return np.stack([inputs.near_root(s, scale, L=L, system=k) for k in range(count)])
+
+
+def eval_tol(L):
+    return 4096 * EPS[L] * 64
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_eval_matches_the_oracle(L):
+    s = make(L, system=0)
+    X = starts(s, L, 5, 1e-2)
+    X = np.concatenate([X, _at(s["root"], L)[None]])
+    J, F = api.poly_eval(dev_system(s), T(X))
+    torch.cuda.synchronize()
+    J, F = J.cpu().numpy(), F.cpu().numpy()
+    tol = eval_tol(L)
+    for p in range(X.shape[0]):
+        Fo, Jo = oracle.poly_eval(s, X[p])
+        assert np.max(np.abs(diff(F[p], Fo))) <= tol, p
+        assert np.max(np.abs(diff(J[p], Jo))) <= tol * 8, p
+    # the root: every monomial value is exact, so is the sum
+    assert np.all(F[-1] == 0.0)
+
+
+def test_eval_at_the_largest_shape():
+    # 64 equations, 63 variables, 64 monomials of 8 variables, degrees 1..3
+    L = 2
+    s = make(L, neq=64, nvar=63, nmon=64, nvpm=8, maxdeg=3, system=4)
+    X = starts(s, L, 3, 1e-2)
+    J, F = api.poly_eval(dev_system(s), T(X))
+    torch.cuda.synchronize()
+    J, F = J.cpu().numpy(), F.cpu().numpy()
+    for p in range(3):
+        Fo, Jo = oracle.poly_eval(s, X[p])
+        assert np.max(np.abs(diff(F[p], Fo))) <= eval_tol(L) * 4
+        assert np.max(np.abs(diff(J[p], Jo))) <= eval_tol(L) * 32
+
+
+@pytest.mark.parametrize("L,iters", [(1, 5), (2, 6), (4, 7)])
+def test_newton_matches_the_oracle_and_converges(L, iters):
+    s = make(L, system=0)
+    X0 = starts(s, L, 6)
+    ds = dev_system(s)
+    root = _at(s["root"], L)
+    # one and two steps: iterates against the oracle's
+    for k in (1, 2):
+        x = T(X0)
+        r = api.newton_batched(ds, x, k)
+        torch.cuda.synchronize()
+        assert np.all(r["info"].cpu().numpy() == 0)
+        xg = x.cpu().numpy()
+        dg = r["dnorm"].cpu().numpy()
+        for p in range(X0.shape[0]):
+            xo, dno = oracle.newton(s, X0[p], k)
+            err = np.sqrt(np.sum(diff(xg[p], xo) ** 2))
+            assert err <= 1e3 * eval_tol(L), (p, k, err)
+            np.testing.assert_allclose(dg[:, p], dno, rtol=1e-6 if L == 1 else 1e-12)
+    # to convergence: every point at the root
+    x = T(X0)
+    r = api.newton_batched(ds, x, iters)
+    torch.cuda.synchronize()
+    xg = x.cpu().numpy()
+    dg = r["dnorm"].cpu().numpy()
+    for p in range(X0.shape[0]):
+        assert np.sqrt(np.sum(diff(xg[p], root) ** 2)) <= FLOOR[L], (p, dg[:, p])
+        assert dg[0, p] > 1e-4 and dg[-1, p] <= FLOOR[L]
+
+
+def test_newton_overdetermined():
+    L = 2
+    s = make(L, neq=40, nvar=32, system=1)
+    X0 = starts(s, L, 4)
+    x = T(X0)
+    r = api.newton_batched(dev_system(s), x, 6)
+    torch.cuda.synchronize()
+    assert np.all(r["info"].cpu().numpy() == 0)
+    xg = x.cpu().numpy()
+    for p in range(4):
+        xo, _ = oracle.newton(s, X0[p], 6)
+        assert np.sqrt(np.sum(diff(xg[p], xo) ** 2)) <= 2 * FLOOR[L]
+        assert np.sqrt(np.sum(diff(xg[p], _at(s["root"], L)) ** 2)) <= FLOOR[L]
+
+
+def test_points_are_independent():
+    L = 2
+    s = make(L, system=2)
+    X0 = starts(s, L, 9)
+    ds = dev_system(s)
+    xa = T(X0)
+    api.newton_batched(ds, xa, 3)
+    xb = T(X0[4:5])
+    api.newton_batched(ds, xb, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(xa[4:5], xb)
+
+
+def test_singular_jacobian_keeps_the_point():
+    # a 33rd variable that no monomial uses: column 33 of J is zero
+    L = 2
+    s = make(L, neq=40, nvar=32, system=3)
+    s["nvar"] = 33
+    X0 = np.concatenate([starts(s, L, 2), np.zeros((2, L, 2, 1))], axis=3)
+    X0[:, 0, 0, 32] = 0.5
+    x = T(X0)
+    r = api.newton_batched(dev_system(s), x, 2)
+    torch.cuda.synchronize()
+    assert np.all(r["info"].cpu().numpy() == 33)
+    assert np.all(np.isnan(r["dnorm"].cpu().numpy()))
+    assert np.array_equal(x.cpu().numpy(), X0)
+
+
+def test_edge_cases():
+    L = 2
+    s = make(L, system=0)
+    ds = dev_system(s)
+    X0 = starts(s, L, 2)
+    x = T(X0)
+    r = api.newton_batched(ds, x, 0)
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), X0) and r["dnorm"].numel() == 0
+    empty = torch.empty((0, L, 2, 32), dtype=torch.float64, device=DEV)
+    api.newton_batched(ds, empty, 3)
+    api.poly_eval(ds, empty)
