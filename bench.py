@@ -142,23 +142,22 @@ def precision_form(torch, api, n=2048, reps=2):
     Qh = f64["Q"].cpu().numpy()
     Qc = (Qh[0] + 1j * Qh[1]).T
     out["fp64_orthogonality"] = float(np.linalg.norm(Qc.conj().T @ Qc - np.eye(n), 2))
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            r = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1) / reps
+
     for L, name in ((2, "dd"), (4, "qd")):
         A = np.zeros((L,) + d["A64"].shape[1:])
         A[0] = d["A64"][0]
         At = torch.from_numpy(A).to(dev)
         bt = torch.from_numpy(np.ascontiguousarray(d["b4"][:L])).to(dev)
-
-        def timed(fn):
-            fn()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
-                r = fn()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            return r, e0.elapsed_time(e1) / reps
-
         fp, tp = timed(lambda: api.lstsq(At, bt))
         fr, tr = timed(lambda: api.refine_lstsq(At, bt, max_iter=30))
         ep = _exact_rel_err(fp["x"].cpu().numpy(), d["x_true"])
@@ -178,6 +177,26 @@ def precision_form(torch, api, n=2048, reps=2):
                      "contraction": [hist[k + 1] / hist[k] for k in range(len(hist) - 1) if hist[k] > 0]}
         print("bench: precision form %s plain %.1f ms err %.2e | refined %.1f ms err %.2e iters %d" %
               (name, tp, ep, tr, er, out[name]["iters"]), file=sys.stderr, flush=True)
+    # the same matrix with a second limb of relative size 2^-60 (below what
+    # the FP64 factorisation sees), b = A x_true still exact in qd
+    del d
+    t_gen = time.perf_counter()
+    dt = inputs.config4(n, workers=min(16, len(os.sched_getaffinity(0))), tail=True)
+    sub = {"workload": "the same A with a second limb a 2^-60 u, u ~ U[-1,1]; b = A x_true exact in qd",
+           "inputs_s": time.perf_counter() - t_gen}
+    for L, name, Ak, bk in ((2, "dd", "A2", "b2"), (4, "qd", "A4", "b4")):
+        At = torch.from_numpy(np.ascontiguousarray(dt[Ak])).to(dev)
+        bt = torch.from_numpy(np.ascontiguousarray(dt[bk])).to(dev)
+        fp, tp = timed(lambda: api.lstsq(At, bt))
+        fr, tr = timed(lambda: api.refine_lstsq(At, bt, max_iter=30))
+        ep = _exact_rel_err(fp["x"].cpu().numpy(), dt["x_true"])
+        er = _exact_rel_err(fr["x"].cpu().numpy(), dt["x_true"])
+        sub[name] = {"plain_ms": tp, "refined_ms": tr, "plain_err": ep, "refined_err": er,
+                     "iters": int(fr["iters"].item()), "info": int(fr["info"].item()), "speedup": tp / tr,
+                     "refined_reaches_plain_error": er <= ep}
+        print("bench: precision form (sub-FP64 limb) %s plain %.1f ms err %.2e | refined %.1f ms err %.2e iters %d"
+              % (name, tp, ep, tr, er, sub[name]["iters"]), file=sys.stderr, flush=True)
+    out["subfp64_A"] = sub
     return out
 
 
@@ -386,9 +405,9 @@ def newton_context(torch, api, steps=None, paths=1024, path_steps=5):
 
 # FP64 flops of one qd 1024 x 1024 factorisation of [A b] (per-panel
 # schedule), counted by rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64
-# lanes, FMA = 2) over all step launches of one mgs_qr call; None until
-# counted (see profiles/).
-QD1024_FLOPS = None
+# lanes, FMA = 2) over all step launches of one mgs_qr call
+# (profiles/mgs_step_qd_1024x1024.md).
+QD1024_FLOPS = 9.635e11
 
 
 def qd_large(torch, api, n=1024, reps=2):

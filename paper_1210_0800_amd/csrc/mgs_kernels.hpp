@@ -45,11 +45,25 @@ __device__ __forceinline__ void static_for(F &&f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// Block barrier for LDS traffic only: waits for this wave's LDS operations,
-// then s_barrier.  Unlike __syncthreads() it does not wait for outstanding
-// global loads, so register loads of a column can stay in flight across it.
+// Waits for this wave's LDS operations (through the builtin, so that the
+// compiler knows they are done; the asm statements keep it from moving
+// memory accesses across the wait).
+__device__ __forceinline__ void lds_wait() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  asm volatile("" ::: "memory");
+}
+
+// Block barrier for LDS traffic only: waits for this wave's LDS operations
+// (s_waitcnt lgkmcnt(0) through the builtin, so that the compiler knows
+// they are done), then s_barrier.  Unlike __syncthreads() it does not wait
+// for outstanding global loads, so register loads of a column can stay in
+// flight across it.  The asm statements keep the compiler from moving
+// memory accesses across it.
 __device__ __forceinline__ void lds_barrier() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  asm volatile("s_barrier" ::: "memory");
 }
 
 struct StepArgs {

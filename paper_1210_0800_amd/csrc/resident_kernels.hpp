@@ -79,16 +79,26 @@ struct ResArgs {
 // data arrived, 2 last projection applied, 3 column handed on (stores
 // issued), 4 column normalised and published, 5 block sums of the last
 // projection past their barrier, 6 square root and reciprocal done.
-constexpr int RES_TRACE_SLOTS = 8;
+constexpr int RES_TRACE_SLOTS = 16;
 #ifdef MGS_TRACE
 #define RES_TRACE(col, slot)                                                                   \
   do {                                                                                         \
     if (a.trace != nullptr && threadIdx.x == 0)                                                \
       a.trace[(size_t)(col) * RES_TRACE_SLOTS + (slot)] = (long long)wall_clock64();           \
   } while (0)
+// The latest of the workgroup's waves to reach this point.
+#define RES_TRACE_LAST(col, slot)                                                                         \
+  do {                                                                                                    \
+    if (a.trace != nullptr && (threadIdx.x & 63) == 0)                                                    \
+      __hip_atomic_fetch_max(a.trace + (size_t)(col) * RES_TRACE_SLOTS + (slot), (long long)wall_clock64(), \
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);                                 \
+  } while (0)
 #else
 #define RES_TRACE(col, slot) \
   do {                       \
+  } while (0)
+#define RES_TRACE_LAST(col, slot) \
+  do {                            \
   } while (0)
 #endif
 
@@ -152,6 +162,20 @@ __device__ __forceinline__ void coh_store(double *p, double v) {
 __device__ __forceinline__ double coh_load(const double *p) {
   return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Waits until every vector memory operation of this wave has completed
+// (s_waitcnt vmcnt(0), expcnt and lgkmcnt left alone).  Through the builtin,
+// not inline asm, so that the compiler knows the loads before it are done:
+// with an opaque wait it treats the columns loaded at the start as still in
+// flight and waits again (for every store the wave has issued since) each
+// time the main loop touches them.
+// The empty asm statements keep the compiler from moving memory accesses
+// across it.
+__device__ __forceinline__ void wait_vmem() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  asm volatile("" ::: "memory");
+}
+
 // The row index of a Q / U access, opaque to the compiler: keeps it from
 // hoisting the 64-bit addresses of every plane and row out of the main
 // loop, which would hold dozens of registers for the whole kernel.
@@ -381,7 +405,7 @@ struct Resident {
   // (atomic max): the owners of later columns do not wait for it (they
   // read the unnormalised columns from U), so their stores can land first.
   __device__ __forceinline__ void publish(int k) {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    wait_vmem();
     if (lane == 0)
       __hip_atomic_fetch_max(a.sync + 16 * wave, (unsigned int)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -497,6 +521,7 @@ struct Resident {
         xch_put(0, ad, false);
       }
     });
+    if (last) RES_TRACE_LAST(ps, 8);
     lds_barrier();
     if (last) RES_TRACE(ps, 5);
     const Rl s2 = P::acc_value_re(xch_tree<0, NW>(1, true));
@@ -508,7 +533,6 @@ struct Resident {
 #pragma unroll
     for (int r = 0; r < RR; ++r) u[r] = P::scale(u[r], inv);
     const C rk = P::scale(d, inv);
-    if (tid == 0) P::store(a.R + (size_t)ps * a.ldr + k, a.planeR, rk);
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
       constexpr int s = decltype(sI)::value;
       if (cidx[s] == ps) {
@@ -518,9 +542,15 @@ struct Resident {
     });
     if (last) {
       RES_TRACE(ps, 2);
+      RES_TRACE_LAST(ps, 9);
       store_u(ps);
       RES_TRACE(ps, 3);
+      RES_TRACE_LAST(ps, 10);
     }
+    // R(k, ps) last: stores count towards the same wait counter as loads,
+    // so a store issued before the hand-off would hold wave 0's rows of U
+    // back until it completes.
+    if (tid == 0) P::store(a.R + (size_t)ps * a.ldr + k, a.planeR, rk);
   }
 
   __device__ __forceinline__ void copy_own(int k, C (&q)[RR]) {
@@ -565,7 +595,7 @@ struct Resident {
   // U (after they have been read: Q may be A), then a grid barrier, so that
   // no entry of Q or U is read before it is either empty or final.
   __device__ __forceinline__ bool mark_empty() {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the columns are in registers
+    wait_vmem();  // the columns are in registers
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
       constexpr int s = decltype(sI)::value;
       const int j = cidx[s];
@@ -586,7 +616,7 @@ struct Resident {
         }
       }
     });
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    wait_vmem();
     __syncthreads();
     bool ok = true;
     if (tid == 0) {
@@ -720,7 +750,10 @@ struct Resident {
       } else if (qsrc == 4) {
         if (opk + 1 == ps) RES_TRACE(ps, 0);
         if (!load_col(a.U, a.ldu, a.planeU, opk, q)) return;
-        if (opk + 1 == ps) RES_TRACE(ps, 1);
+        if (opk + 1 == ps) {
+          RES_TRACE(ps, 1);
+          RES_TRACE_LAST(ps, 7);
+        }
       }
       if (mode == 1) {
         apply(q, opk, lo, RES_NONE);

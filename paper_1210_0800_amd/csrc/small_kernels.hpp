@@ -101,7 +101,7 @@ __global__ __launch_bounds__(64 * SMALL_WAVES) void mgs_small_kernel(SmallArgs a
           d.im = P::rzero();
           P::store(a.R + (size_t)c * a.ldr + c, a.planeR, d);
         }
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        lds_wait();
         if (lane == 0) __hip_atomic_store(&flag[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     });
