@@ -99,18 +99,21 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
  *   work      workspace of mgs_workspace_size(m, n, prec, MGS_OP_QR) bytes
  *             (always required: it holds the working copy of b, the
  *             publication counters of the single-launch factorisation and,
- *             in dd with m <= 1024, its hand-off copy of the columns,
- *             32 m n bytes).
+ *             in dd with m <= 1024 and in double with m <= 2048 and
+ *             16 m n <= 32 MiB, its hand-off copy of the columns, 16 prec
+ *             m n bytes).
  *   info      device int, see above.
  * prec 1, 2 or 4.  Requires 1 <= n <= m <= MGS_MAX_ROWS_{DD,QD}.
  * Schedule: with m <= 64 and at most 64 columns of [A b] (and, in qd, the
  * q vectors within 159 KiB: 64 m n bytes), one workgroup (a column per wave
  * slot, q vectors through LDS; for double and qd the kernel of
- * mgs_lstsq_batched on one system); in dd when
- * every column fits in the register file of the device (m <= 1024 and at
- * most 5 columns per compute unit, 8 when m <= 512, e.g. 1024 x 1024 with b
- * on 256 compute units) one cooperative launch with the columns held in
- * registers; otherwise (and in qd) one launch per panel of columns.
+ * mgs_lstsq_batched on one system); in dd and double when
+ * every column fits in the register file of the device (dd: m <= 1024 and
+ * at most 5 columns per compute unit, 8 when m <= 512, e.g. 1024 x 1024
+ * with b on 256 compute units; double: m <= 2048, 5 columns per compute
+ * unit beyond 1024 rows, 8 below) one cooperative launch with the columns
+ * held in registers; otherwise (and in qd) one launch per panel of
+ * columns.
  * mgs_qr_schedule (below) forces one of them.
  * All schedules apply the projections of Figure 1 in the same order per
  * column; reduction trees differ, and in the single launch the last twelve
@@ -246,7 +249,9 @@ int mgs_refine_solve(int m, int n, int prec, const double *A, int lda, const dou
  *   y  [out]  n planar: y = Q^H b as the projections of b (required when
  *             b != NULL, ignored otherwise).
  *   block     panel width; must be 64 (MGS_ERR_PREC otherwise).
- *   work      mgs_workspace_size(m, n, 1, MGS_OP_QR64, .) bytes.
+ *   work      mgs_workspace_size(m, n, 1, MGS_OP_QR64, .) bytes (the FP64
+ *             factors and, for m <= 2048, the hand-off area of the single
+ *             launch that factors each panel).
  *   info      device int: 0, or k > 0 when column k had a zero or
  *             non-finite norm.
  * Requires 1 <= n <= m <= MGS_MAX_ROWS_DD.

@@ -44,28 +44,6 @@ __global__ __launch_bounds__(256) void bs_mark_kernel(int n, double *x, int *inf
   }
 }
 
-template <class P>
-__device__ __forceinline__ typename P::C bs_coh_load(const double *p, size_t plane, bool &miss) {
-  constexpr int NP = 2 * P::L;
-  // plane q of the element, gathered in plane order, then read as P::load
-  // reads a planar element with plane stride 1
-  double t[NP];
-#pragma unroll
-  for (int q = 0; q < NP; ++q) {
-    t[q] = coh_load(p + (size_t)q * plane);
-    miss = miss || __double_as_longlong(t[q]) == RES_EMPTY;
-  }
-  return P::load(t, 1);
-}
-template <class P>
-__device__ __forceinline__ void bs_coh_store(double *p, size_t plane, const typename P::C &v) {
-  constexpr int NP = 2 * P::L;
-  double t[NP];
-  P::store(t, 1, v);
-#pragma unroll
-  for (int q = 0; q < NP; ++q) coh_store(p + (size_t)q * plane, t[q]);
-}
-
 // True when any limb of v carries the empty marker.
 template <class P>
 __device__ __forceinline__ bool bs_empty(const typename P::C &v) {
@@ -140,7 +118,7 @@ __global__ __launch_bounds__(BP_ROWS) void trsv_pipe_kernel(int n, const double 
   auto xload = [&](int col) __attribute__((always_inline)) {
     bool m = false;
     const int cl = col < 0 ? 0 : (col >= n ? n - 1 : col);
-    return bs_coh_load<P>(x + cl, (size_t)n, m);
+    return res_coh_load<P>(x + cl, (size_t)n, m);
   };
   // The block's own columns in solve order in a ring (slot t: the t-th,
   // (t+8)-th, ... column).
@@ -239,7 +217,7 @@ __global__ __launch_bounds__(BP_ROWS) void trsv_pipe_kernel(int n, const double 
       C yn = yv;
       P::upd(yn, rb[t], xk);
       yv = bs_pick<P>(FWD ? lane > k : lane < k, yn, yv);
-      if (mine) bs_coh_store<P>(x + i, (size_t)n, xown);
+      if (mine) res_coh_store<P>(x + i, (size_t)n, xown);
       rb[t] = rload(cc + DIR * BP_RING);
       cc += DIR;
     }

@@ -44,33 +44,6 @@ struct BatArgs {
   long long spin_ticks;
 };
 
-// One DPP step of a wave sum for any accumulator: every double of the
-// accumulator (the real half only when re_only) moves by CTRL, then the
-// merge.  Lanes shifted in from outside a row read zero.
-template <class P, int CTRL, int ROWS>
-__device__ __forceinline__ void dpp_step_any(typename P::Acc &a, bool re_only) {
-  using Acc = typename P::Acc;
-  constexpr int NA = sizeof(Acc) / sizeof(double);
-  Acc o;
-  double *po = reinterpret_cast<double *>(&o);
-  const double *pa = reinterpret_cast<const double *>(&a);
-#pragma unroll
-  for (int c = 0; c < NA; ++c) po[c] = (re_only && c >= NA / 2) ? 0.0 : dpp_shift<CTRL, ROWS>(pa[c]);
-  if (re_only)
-    P::acc_merge_re(a, o);
-  else
-    P::acc_merge(a, o);
-}
-// Wave sum into lane 63 (fixed tree: row scans, then the row totals).
-template <class P>
-__device__ __forceinline__ void wave_sum_any(typename P::Acc &a, bool re_only) {
-  dpp_step_any<P, 0x111, 0xf>(a, re_only);  // row_shr:1
-  dpp_step_any<P, 0x112, 0xf>(a, re_only);  // row_shr:2
-  dpp_step_any<P, 0x114, 0xf>(a, re_only);  // row_shr:4
-  dpp_step_any<P, 0x118, 0xf>(a, re_only);  // row_shr:8
-  dpp_step_any<P, 0x142, 0xa>(a, re_only);  // row_bcast:15 into rows 1, 3
-  dpp_step_any<P, 0x143, 0xc>(a, re_only);  // row_bcast:31 into rows 2, 3
-}
 // Lane 63's accumulator, wave-uniform.
 template <class P>
 __device__ __forceinline__ typename P::Acc acc_lane63(const typename P::Acc &v) {

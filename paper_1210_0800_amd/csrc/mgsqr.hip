@@ -237,11 +237,14 @@ int project_launch(int m, int n, const double *Q, int ldq, const double *b, doub
 }
 
 // QR: working copy of b (2Lm doubles), then the synchronisation words of
-// the single-launch schedule, then (dd, m <= 1024: the shapes that can take
-// it) its hand-off copy of the n columns (2Lmn doubles).
+// the single-launch schedule, then (the shapes that can take it: dd with
+// m <= 1024, FP64 with m <= 2048 and at most 32 MiB) its hand-off copy of
+// the n columns (2Lmn doubles).
 size_t qr_w_bytes(int m, int prec) { return round256(sizeof(double) * 2 * (size_t)prec * m); }
+bool res_rows_ok(int m, int prec) { return (prec == 2 && m <= 1024) || (prec == 1 && m <= 2048); }
 size_t qr_u_bytes(int m, int n, int prec) {
-  return (prec == 2 && m <= 1024) ? round256(sizeof(double) * 2 * (size_t)prec * m * n) : 0;
+  const size_t u = round256(sizeof(double) * 2 * (size_t)prec * m * n);
+  return (res_rows_ok(m, prec) && u <= ((size_t)32 << 20)) ? u : 0;
 }
 size_t qr_work_bytes(int m, int n, int prec) {
   return qr_w_bytes(m, prec) + sizeof(unsigned int) * RES_SYNC_WORDS + qr_u_bytes(m, n, prec);
@@ -304,8 +307,16 @@ struct RefineWork {
   double *Q64, *R64, *y64, *d64, *r64;
   void *partial;
   RefineCtl *ctl;
+  void *res;  // the FP64 panels' single launch: synchronisation words, then U (nullptr: none)
   size_t bytes;
 };
+// Synchronisation words and hand-off copy U of one FP64 panel (m x NBP)
+// for the single-launch panel factorisation (m <= 2048), else nothing.
+size_t panel_res_bytes(int m, int n) {
+  if (m > 2048) return 0;
+  const int nb = n < NBP ? n : NBP;
+  return round256(sizeof(unsigned int) * RES_SYNC_WORDS) + round256(sizeof(double) * 2 * (size_t)m * nb);
+}
 RefineWork refine_layout(int m, int n, int prec, void *base) {
   const int nchunk = ceil_div(n, NBP);
   const size_t acc_bytes = sizeof(PrecQD::Acc);  // the residual accumulates in qd
@@ -324,14 +335,20 @@ RefineWork refine_layout(int m, int n, int prec, void *base) {
   w.r64 = reinterpret_cast<double *>(take(sizeof(double) * 2 * (size_t)m));
   w.partial = take(acc_bytes * (size_t)nchunk * m);
   w.ctl = reinterpret_cast<RefineCtl *>(take(sizeof(RefineCtl)));
+  w.res = panel_res_bytes(m, n) > 0 ? take(panel_res_bytes(m, n)) : nullptr;
   w.bytes = off;
   return w;
 }
 
-// mgs_qr64: Q64 (m x (n+1)) and R64 (n x (n+1)), FP64 complex.
+// mgs_qr64: Q64 (m x (n+1)) and R64 (n x (n+1)), FP64 complex, then the
+// panel factorisation's single-launch area.
 size_t qr64_work_bytes(int m, int n) {
-  return round256(sizeof(double) * 2 * (size_t)m * (n + 1)) + round256(sizeof(double) * 2 * (size_t)n * (n + 1));
+  return round256(sizeof(double) * 2 * (size_t)m * (n + 1)) + round256(sizeof(double) * 2 * (size_t)n * (n + 1)) +
+         panel_res_bytes(m, n);
 }
+
+template <class P>
+int res_launch(const StepArgs &s, void *sync, double *u, hipStream_t st);
 
 // FP64 blocked MGS of [A64 b64] held in Q64 (m x (n+1)); R64 (n x (n+1))
 // receives R and, in its last column, y.
@@ -362,15 +379,23 @@ int factor64(int m, int n, const RefineWork &w, int *info, hipStream_t st) {
     a.t = 0;
     a.kbase = k0;
     a.init_info = 0;
-    int rc = dispatch_shape<PrecD>(a, sh, st);
+    // The panel in one cooperative launch when it fits, else one launch
+    // per column pair.
+    int rc = 1;
+    if (w.res != nullptr) {
+      double *u = reinterpret_cast<double *>(static_cast<char *>(w.res) +
+                                             round256(sizeof(unsigned int) * RES_SYNC_WORDS));
+      rc = res_launch<PrecD>(a, w.res, u, st);
+    }
+    if (rc == 1) rc = dispatch_shape<PrecD>(a, sh, st);
     if (rc != MGS_OK) return rc;
     const int N = n + 1 - (k0 + nb);  // trailing columns, b included
     if (N > 0) {
       const double *Qp = w.Q64 + (size_t)k0 * m;
       double *At = w.Q64 + (size_t)(k0 + nb) * m;
       double *Wb = w.R64 + (size_t)(k0 + nb) * n + k0;
-      hipLaunchKernelGGL(zgemm_qha_kernel, dim3(ceil_div(N, 16)), dim3(256 * QHA_SLICES), 0, st, m, N, nb, Qp, m, At,
-                         m, planeQ, Wb, n, planeR);
+      hipLaunchKernelGGL(zgemm_qha_kernel, dim3(ceil_div(N, 16), ceil_div(nb, 16)), dim3(64 * QHA_SLICES), 0, st, m, N,
+                         nb, Qp, m, At, m, planeQ, Wb, n, planeR);
       const int tiles = ceil_div(m, 16) * ceil_div(N, 16);
       hipLaunchKernelGGL(zgemm_update_kernel, dim3(ceil_div(tiles, 4)), dim3(256), 0, st, m, N, nb, Qp, m, At, m,
                          planeQ, Wb, n, planeR);
@@ -460,20 +485,22 @@ int res_max_cols(int ncols, int bw, int G) {
 // lane).  Short columns take fewer waves (64 nw >= m), so that their block
 // sums have fewer levels and their barriers fewer waves.
 constexpr int RES_NW = 8;
-constexpr int res_cb(int rr) { return rr == 1 ? 8 : 5; }
+// Column slots: 80 registers of columns per lane (dd: RR x CB <= 10 of 8
+// registers; FP64: RR x CB <= 20 of 4), at most 8 slots.
+constexpr int res_cb(int L, int rr) { return L == 2 ? (rr == 1 ? 8 : 5) : (rr <= 2 ? 8 : 5); }
 
 struct ResPlan {
   int rr, nw, bw, np, G;
 };
-bool res_choose(int m, int ncols, int cus, ResPlan &pl) {
+bool res_choose(int m, int ncols, int L, int cus, ResPlan &pl) {
   const int rr = pow2_at_least(ceil_div(m, 64 * RES_NW));
-  if (rr > 2) return false;
+  if (rr > (L == 1 ? 4 : 2)) return false;
   int nw = RES_NW;
   if (rr == 1) {
     nw = pow2_at_least(ceil_div(m, 64));
     if (nw > RES_NW) nw = RES_NW;
   }
-  const int cb = res_cb(rr);
+  const int cb = res_cb(L, rr);
   // Panels of one column: the look-ahead hand-off of the kernel assumes it.
   const int bws[1] = {1};
   for (int bw : bws) {
@@ -501,7 +528,7 @@ long long *g_trace = nullptr;
 // takes the per-panel schedule).
 template <class P, int RR, int NW>
 int res_launch_rr(ResArgs a, int cus, hipStream_t st) {
-  constexpr int CB = res_cb(RR);
+  constexpr int CB = res_cb(P::L, RR);
   auto kern = mgs_resident_kernel<P, RR, CB, NW>;
   // Only kernels that keep everything in registers and LDS take this
   // schedule: no private (scratch) memory in a cooperative launch.
@@ -513,7 +540,7 @@ int res_launch_rr(ResArgs a, int cus, hipStream_t st) {
       hipSuccess)
     return 1;
   if ((long long)per_cu * cus < a.G) return 1;
-  hipLaunchKernelGGL(resident_init_kernel, dim3(1), dim3(RES_SYNC_WORDS), 0, st, a.sync, a.info, 1);
+  hipLaunchKernelGGL(resident_init_kernel, dim3(1), dim3(RES_SYNC_WORDS), 0, st, a.sync, a.info, a.init_info);
   if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
   void *args[] = {&a};
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(a.G), dim3(64 * NW), args, 0, st) !=
@@ -524,13 +551,14 @@ int res_launch_rr(ResArgs a, int cus, hipStream_t st) {
   return MGS_OK;
 }
 
-// dd only: the qd instantiations do not fit in registers.
-int res_launch_dd(const StepArgs &s, void *sync, double *u, hipStream_t st) {
-  using P = PrecDD;
+// FP64 and dd only: the qd instantiations do not fit in registers.
+template <class P>
+int res_launch(const StepArgs &s, void *sync, double *u, hipStream_t st) {
+  static_assert(P::L <= 2, "no qd instantiation of the single launch");
   DevInfo d;
   if (!dev_info(d) || d.cus <= 0) return 1;
   ResPlan pl;
-  if (!res_choose(s.m, s.ncols, d.cus, pl)) return 1;
+  if (!res_choose(s.m, s.ncols, P::L, d.cus, pl)) return 1;
   ResArgs a;
   a.m = s.m;
   a.n = s.n;
@@ -558,9 +586,14 @@ int res_launch_dd(const StepArgs &s, void *sync, double *u, hipStream_t st) {
   a.xcd_group = pl.G % 8 == 0 ? pl.G / 8 : 0;
   a.defer = 12;
   a.spin_ticks = d.wclk_khz * 2000;  // 2 s
+  a.kbase = s.kbase;
+  a.init_info = s.init_info;
 #ifdef MGS_TRACE
   a.trace = g_trace;
 #endif
+  if constexpr (P::L == 1) {
+    if (pl.rr == 4) return res_launch_rr<P, 4, 8>(a, d.cus, st);
+  }
   if (pl.rr == 2) return res_launch_rr<P, 2, 8>(a, d.cus, st);
   switch (pl.nw) {
     case 1: return res_launch_rr<P, 1, 1>(a, d.cus, st);
@@ -818,7 +851,8 @@ int mgs_qr_schedule(int m, int n, int prec, const double *A, int lda, double *Q,
   if (mode == MGS_SCHED_AUTO || mode == MGS_SCHED_RESIDENT) {
     void *sync = static_cast<char *>(work) + qr_w_bytes(m, prec);
     double *u = reinterpret_cast<double *>(static_cast<char *>(sync) + sizeof(unsigned int) * RES_SYNC_WORDS);
-    const int rc = prec == 2 && qr_u_bytes(m, n, prec) > 0 ? res_launch_dd(a, sync, u, st) : 1;
+    int rc = 1;
+    if (qr_u_bytes(m, n, prec) > 0) rc = prec == 2 ? res_launch<PrecDD>(a, sync, u, st) : res_launch<PrecD>(a, sync, u, st);
     if (rc != 1) return rc;
     if (mode == MGS_SCHED_RESIDENT) return MGS_ERR_DIMS;
   }
@@ -918,6 +952,9 @@ int mgs_qr64(int m, int n, const double *A, int lda, const double *b, double *Q,
   RefineWork w;
   w.Q64 = static_cast<double *>(work);
   w.R64 = reinterpret_cast<double *>(static_cast<char *>(work) + round256(sizeof(double) * 2 * (size_t)m * (n + 1)));
+  w.res = panel_res_bytes(m, n) > 0 ? static_cast<char *>(work) + round256(sizeof(double) * 2 * (size_t)m * (n + 1)) +
+                                          round256(sizeof(double) * 2 * (size_t)n * (n + 1))
+                                    : nullptr;
   hipLaunchKernelGGL(copy64_in_kernel, dim3(ceil_div(m, 256), n + 1), dim3(256), 0, st, m, n, A, lda, b, w.Q64, info);
   if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
   const int rc = factor64(m, n, w, info, st);

@@ -31,28 +31,29 @@ constexpr int NBP = 64;  // panel width of the blocked factorisation
 // W (NBP x N) = Q_p^H (NBP x m) A_t (m x N), complex, planar FP64.
 // Q_p: the panel's first column (plane stride plane), A_t: the first
 // trailing column, W: output with leading dimension ldw (R's block row).
-// One workgroup = 16 waves for one 16-column tile of W: wave w computes
-// the row tile w % 4 (16 panel columns) over the K slice w / 4 (a quarter
-// of the m rows, in steps of 4); the four slice partials are then summed
-// in slice order through LDS, so the result does not depend on timing.
-constexpr int QHA_SLICES = 4;
-__global__ __launch_bounds__(256 * QHA_SLICES) void zgemm_qha_kernel(int m, int N, int nbp, const double *Qp, int ldq,
-                                                                      const double *At, int lda, size_t plane,
-                                                                      double *W, int ldw, size_t planeW) {
-  __shared__ double red[QHA_SLICES - 1][4][64][8];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tr = wave & 3, ks = wave >> 2;
-  const int i0 = tr * 16;            // panel column tile
-  const int j0 = blockIdx.x * 16;    // trailing column tile
+// One workgroup per 16 x 16 tile of W (grid: trailing column tiles x panel
+// column tiles, 4 x 124 = 496 workgroups for the first 2048 panel, enough
+// to occupy every compute unit); its QHA_SLICES waves each reduce over one
+// slice of the m rows (a multiple of 4), and the slice partials are then
+// summed in slice order through LDS, so the result does not depend on
+// timing.
+constexpr int QHA_SLICES = 8;
+__global__ __launch_bounds__(64 * QHA_SLICES) void zgemm_qha_kernel(int m, int N, int nbp, const double *Qp, int ldq,
+                                                                     const double *At, int lda, size_t plane,
+                                                                     double *W, int ldw, size_t planeW) {
+  __shared__ double red[QHA_SLICES - 1][64][8];
+  const int lane = threadIdx.x & 63, ks = threadIdx.x >> 6;
+  const int i0 = blockIdx.y * 16;  // panel column tile
+  const int j0 = blockIdx.x * 16;  // trailing column tile
   const int li = lane & 15, lk = lane >> 4;
-  const int qc = i0 + li;            // panel column read by this lane (A operand)
-  const int tc = j0 + li;            // trailing column read by this lane (B operand)
+  const int qc = i0 + li;  // panel column read by this lane (A operand)
+  const int tc = j0 + li;  // trailing column read by this lane (B operand)
   const bool qok = qc < nbp, tok = tc < N;
   const int mq = ((m + 4 * QHA_SLICES - 1) / (4 * QHA_SLICES)) * 4;  // rows per slice, multiple of 4
   const int k0 = ks * mq, k1 = min(m, k0 + mq);
   v4d cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
-  const double *qr = Qp + (size_t)qc * ldq, *qi = qr + plane;
-  const double *ar = At + (size_t)tc * lda, *ai = ar + plane;
+  const double *qr = Qp + (size_t)(qok ? qc : 0) * ldq, *qi = qr + plane;
+  const double *ar = At + (size_t)(tok ? tc : 0) * lda, *ai = ar + plane;
 #pragma unroll 4
   for (int k = k0; k < k1; k += 4) {
     const int row = k + lk;
@@ -68,8 +69,8 @@ __global__ __launch_bounds__(256 * QHA_SLICES) void zgemm_qha_kernel(int m, int 
   if (ks > 0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      red[ks - 1][tr][lane][r] = cr[r];
-      red[ks - 1][tr][lane][4 + r] = ci[r];
+      red[ks - 1][lane][r] = cr[r];
+      red[ks - 1][lane][4 + r] = ci[r];
     }
   }
   __syncthreads();
@@ -78,8 +79,8 @@ __global__ __launch_bounds__(256 * QHA_SLICES) void zgemm_qha_kernel(int m, int 
   for (int s = 0; s < QHA_SLICES - 1; ++s) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      cr[r] += red[s][tr][lane][r];
-      ci[r] += red[s][tr][lane][4 + r];
+      cr[r] += red[s][lane][r];
+      ci[r] += red[s][lane][4 + r];
     }
   }
   const int oc = j0 + li;

@@ -67,6 +67,8 @@ struct ResArgs {
   unsigned int *sync;  // RES_SYNC_WORDS words, zero at launch: per-wave counters and the abort flag
   int bw, np, G;  // bw must be 1: every panel is one column
   int xcd_group;        // logical workgroups per XCD (G / 8), 0 for identity numbering
+  int kbase;            // column offset of this matrix in the caller's, for info
+  int init_info;        // clear info at the start (else keep an earlier status)
   int defer;            // look-ahead window of the critical-path-first rule (columns, >= 1)
   long long spin_ticks;  // wall-clock limit of one wait
 #ifdef MGS_TRACE
@@ -244,26 +246,55 @@ __device__ __forceinline__ double dpp_shift(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void dpp_step(PrecDD::Acc &a, bool re_only) {
-  PrecDD::Acc o;
-  o.sr = dpp_shift<CTRL, ROWS>(a.sr);
-  o.cr = dpp_shift<CTRL, ROWS>(a.cr);
-  if (re_only) {
-    PrecDD::acc_merge_re(a, o);
-  } else {
-    o.si = dpp_shift<CTRL, ROWS>(a.si);
-    o.ci = dpp_shift<CTRL, ROWS>(a.ci);
-    PrecDD::acc_merge(a, o);
-  }
+// One DPP step of a wave sum for any accumulator: every double of the
+// accumulator (the real half only when re_only) moves by CTRL, then the
+// merge.  Lanes shifted in from outside a row read zero.
+template <class P, int CTRL, int ROWS>
+__device__ __forceinline__ void dpp_step_any(typename P::Acc &a, bool re_only) {
+  using Acc = typename P::Acc;
+  constexpr int NA = sizeof(Acc) / sizeof(double);
+  Acc o;
+  double *po = reinterpret_cast<double *>(&o);
+  const double *pa = reinterpret_cast<const double *>(&a);
+#pragma unroll
+  for (int c = 0; c < NA; ++c) po[c] = (re_only && c >= NA / 2) ? 0.0 : dpp_shift<CTRL, ROWS>(pa[c]);
+  if (re_only)
+    P::acc_merge_re(a, o);
+  else
+    P::acc_merge(a, o);
 }
-__device__ __forceinline__ void wave_sum_dpp(PrecDD::Acc &a, bool re_only) {
-  dpp_step<0x111, 0xf>(a, re_only);  // row_shr:1
-  dpp_step<0x112, 0xf>(a, re_only);  // row_shr:2
-  dpp_step<0x114, 0xf>(a, re_only);  // row_shr:4
-  dpp_step<0x118, 0xf>(a, re_only);  // row_shr:8
-  dpp_step<0x142, 0xa>(a, re_only);  // row_bcast:15 into rows 1, 3
-  dpp_step<0x143, 0xc>(a, re_only);  // row_bcast:31 into rows 2, 3
+// Wave sum into lane 63 (fixed tree: row scans, then the row totals).
+template <class P>
+__device__ __forceinline__ void wave_sum_any(typename P::Acc &a, bool re_only) {
+  dpp_step_any<P, 0x111, 0xf>(a, re_only);  // row_shr:1
+  dpp_step_any<P, 0x112, 0xf>(a, re_only);  // row_shr:2
+  dpp_step_any<P, 0x114, 0xf>(a, re_only);  // row_shr:4
+  dpp_step_any<P, 0x118, 0xf>(a, re_only);  // row_shr:8
+  dpp_step_any<P, 0x142, 0xa>(a, re_only);  // row_bcast:15 into rows 1, 3
+  dpp_step_any<P, 0x143, 0xc>(a, re_only);  // row_bcast:31 into rows 2, 3
+}
+
+// One complex element of a planar array (2L planes, stride `plane`) with
+// device-scope loads / stores, plane by plane; `miss` is set when a plane
+// holds the empty marker.
+template <class P>
+__device__ __forceinline__ typename P::C res_coh_load(const double *p, size_t plane, bool &miss) {
+  constexpr int NP = 2 * P::L;
+  double t[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    t[q] = coh_load(p + (size_t)q * plane);
+    miss = miss || __double_as_longlong(t[q]) == RES_EMPTY;
+  }
+  return P::load(t, 1);
+}
+template <class P>
+__device__ __forceinline__ void res_coh_store(double *p, size_t plane, const typename P::C &v, bool unmark = false) {
+  constexpr int NP = 2 * P::L;
+  double t[NP];
+  P::store(t, 1, v);
+#pragma unroll
+  for (int q = 0; q < NP; ++q) coh_store(p + (size_t)q * plane, unmark ? res_unmark(t[q]) : t[q]);
 }
 
 template <class P, int RR, int CB, int NW>
@@ -324,7 +355,7 @@ struct Resident {
   }
   __device__ __forceinline__ void reduce_slot(int s, bool re_only) {
     Acc t = red_tree<0, NW>(s, re_only);
-    wave_sum_dpp(t, re_only);
+    wave_sum_any<P>(t, re_only);
     if (lane == 63) rsum[s] = t;
   }
 
@@ -374,7 +405,7 @@ struct Resident {
   // sum.  Two buffers alternate: a wave can only overwrite one after every
   // wave has passed the next barrier, i.e. finished reading it.
   __device__ __forceinline__ void xch_put(int pos, Acc t, bool re_only) {
-    wave_sum_dpp(t, re_only);
+    wave_sum_any<P>(t, re_only);
     if (lane == 63) {
       const double *d = reinterpret_cast<const double *>(&t);
 #pragma unroll
@@ -426,17 +457,7 @@ struct Resident {
         for (int r = 0; r < RR; ++r) {
           const int i = row_of(r, RWG);
           if (i < a.m) {
-            C v = col[s][r];
-            if (raw) {
-              v.re.h = res_unmark(v.re.h);
-              v.im.h = res_unmark(v.im.h);
-              v.re.l = res_unmark(v.re.l);
-              v.im.l = res_unmark(v.im.l);
-            }
-            coh_store(dst + i, v.re.h);
-            coh_store(dst + i + a.planeU, v.im.h);
-            coh_store(dst + i + 2 * a.planeU, v.re.l);
-            coh_store(dst + i + 3 * a.planeU, v.im.l);
+            res_coh_store<P>(dst + i, a.planeU, col[s][r], raw);
           }
         }
       }
@@ -461,9 +482,9 @@ struct Resident {
     lds_barrier();
     const Rl s2 = P::acc_value_re(xch_tree<0, NW>(0, true));
     xb ^= 1;
-    if (!P::ok_norm(s2) && tid == 0) info_first_bad(a.info, x + 1);
+    if (!P::ok_norm(s2) && tid == 0) info_first_bad(a.info, a.kbase + x + 1);
     Rl rkk, inv;
-    P::sqrt_recip(s2, rkk, inv);
+    root_and_inverse<P>(s2, rkk, inv);
     static_for<CB>([&](auto sI) __attribute__((always_inline)) {
       constexpr int s = decltype(sI)::value;
       if (cidx[s] == x) {
@@ -478,12 +499,7 @@ struct Resident {
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
       const int i = row_of(r, RWG);
-      if (i < a.m) {
-        coh_store(dst + i, q[r].re.h);
-        coh_store(dst + i + a.planeQ, q[r].im.h);
-        coh_store(dst + i + 2 * a.planeQ, q[r].re.l);
-        coh_store(dst + i + 3 * a.planeQ, q[r].im.l);
-      }
+      if (i < a.m) res_coh_store<P>(dst + i, a.planeQ, q[r]);
     }
     if (tid == 0) {
       C d;
@@ -528,7 +544,7 @@ struct Resident {
     const C d = P::acc_value(xch_tree<0, NW>(0, false));
     xb ^= 1;
     Rl rkk, inv;
-    P::sqrt_recip(s2, rkk, inv);
+    root_and_inverse<P>(s2, rkk, inv);
     if (last) RES_TRACE(ps, 6);
 #pragma unroll
     for (int r = 0; r < RR; ++r) u[r] = P::scale(u[r], inv);
@@ -575,15 +591,7 @@ struct Resident {
       for (int r = 0; r < RR; ++r) {
         const int i = row_of(r, RWG);
         q[r] = P::czero();
-        if (i < a.m) {
-          q[r].re.h = coh_load(src + i);
-          q[r].im.h = coh_load(src + i + plane);
-          q[r].re.l = coh_load(src + i + 2 * plane);
-          q[r].im.l = coh_load(src + i + 3 * plane);
-          miss = miss || __double_as_longlong(q[r].re.h) == RES_EMPTY ||
-                 __double_as_longlong(q[r].im.h) == RES_EMPTY || __double_as_longlong(q[r].re.l) == RES_EMPTY ||
-                 __double_as_longlong(q[r].im.l) == RES_EMPTY;
-        }
+        if (i < a.m) q[r] = res_coh_load<P>(src + i, plane, miss);
       }
       if (__ballot(miss) == 0) return true;
       if (t0 < 0) t0 = wall_clock64();
@@ -608,7 +616,7 @@ struct Resident {
           const int i = r * RWG + tid;
           if (i < a.m) {
 #pragma unroll
-            for (int pl = 0; pl < 4; ++pl) {
+            for (int pl = 0; pl < 2 * P::L; ++pl) {
               coh_store(dst + i + pl * a.planeQ, e);
               coh_store(dsu + i + pl * a.planeU, e);
             }

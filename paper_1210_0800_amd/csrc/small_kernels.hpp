@@ -81,7 +81,7 @@ __global__ __launch_bounds__(64 * SMALL_WAVES) void mgs_small_kernel(SmallArgs a
         Acc t;
         P::acc_zero(t);
         P::acc_abs2(t, col[s]);
-        wave_sum_dpp(t, true);
+        wave_sum_any<PrecDD>(t, true);
         const Rl s2 = P::acc_value_re(small_lane63(t));
         if (!P::ok_norm(s2) && lane == 0) atomicCAS(a.info, 0, c + 1);
         Rl rkk, inv;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(64 * SMALL_WAVES) void mgs_small_kernel(SmallArgs a
         Acc t;
         P::acc_zero(t);
         P::acc_cmulc(t, q, col[s]);
-        wave_sum_dpp(t, false);
+        wave_sum_any<PrecDD>(t, false);
         const C rk = P::acc_value(small_lane63(t));
         if (lane == 0) {
           if (j < a.n)
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(64 * SMALL_WAVES) void mgs_small_kernel(SmallArgs a
         Acc t;
         P::acc_zero(t);
         P::acc_abs2(t, col[s]);
-        wave_sum_dpp(t, true);
+        wave_sum_any<PrecDD>(t, true);
         const Rl s2 = P::acc_value_re(small_lane63(t));
         if (lane == 0) P::store_real(a.rho, 1, P::ok_norm(s2) ? P::sqrt_(s2) : P::rzero());
       }

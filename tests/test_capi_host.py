@@ -161,8 +161,12 @@ def test_mgs_qr64_rejects_bad_arguments():
     assert call(wb=64) == -4
     # b == NULL: y may be NULL (fails later on the workspace, not the pointer)
     assert call(b=None, y=None, wb=64) == -4
-    # Q64 (8 x 5) and R64 (4 x 5) complex FP64, each rounded up to 256 bytes
-    assert _lib.workspace_size(8, 4, 1, _lib.MGS_OP_QR64) == 768 + 512
+    # Q64 (8 x 5) and R64 (4 x 5) complex FP64, each rounded up to 256 bytes,
+    # then the panel single launch's sync words (1 KiB) and hand-off copy of
+    # the panel (2 m min(n, 64) doubles)
+    assert _lib.workspace_size(8, 4, 1, _lib.MGS_OP_QR64) == 768 + 512 + 1024 + 512
+    # no single launch beyond 2048 rows
+    assert _lib.workspace_size(2049, 4, 1, _lib.MGS_OP_QR64) == (2 * 2049 * 5 * 8 + 255) // 256 * 256 + 512
     with pytest.raises(_lib.MgsError):
         _lib.workspace_size(8, 4, 2, _lib.MGS_OP_QR64)
 
@@ -170,7 +174,12 @@ def test_mgs_qr64_rejects_bad_arguments():
 def test_prec1_workspaces_and_refusals():
     # complex double (prec 1): QR and SOLVE only; the adjoint and the
     # precision form stay dd / qd
-    assert _lib.workspace_size(32, 32, 1, _lib.MGS_OP_QR) == 2 * 32 * 8 + 1024
+    # b copy, sync words, and (m <= 2048, at most 32 MiB) the single
+    # launch's hand-off copy of the n columns
+    assert _lib.workspace_size(32, 32, 1, _lib.MGS_OP_QR) == 2 * 32 * 8 + 1024 + 2 * 32 * 32 * 8
+    assert _lib.workspace_size(2048, 1024, 1, _lib.MGS_OP_QR) == 2 * 2048 * 8 + 1024 + 2 * 2048 * 1024 * 8
+    assert _lib.workspace_size(2048, 1025, 1, _lib.MGS_OP_QR) == 2 * 2048 * 8 + 1024
+    assert _lib.workspace_size(2049, 10, 1, _lib.MGS_OP_QR) == (2 * 2049 * 8 + 255) // 256 * 256 + 1024
     assert _lib.workspace_size(32, 32, 1, _lib.MGS_OP_SOLVE) == 512
     with pytest.raises(_lib.MgsError):
         _lib.workspace_size(32, 32, 1, _lib.MGS_OP_ADJOINT)

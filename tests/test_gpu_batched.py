@@ -150,7 +150,7 @@ def test_empty_batch_and_refusals():
 
 # ------------------------------------------------ complex double, prec 1 --
 # The paper's third precision (Table 4: n = 16 .. 256, square systems).
-FP64_SHAPES = [(16, 16), (32, 32), (80, 80), (128, 128), (256, 256), (300, 200), (1030, 40)]
+FP64_SHAPES = [(16, 16), (32, 32), (80, 80), (128, 128), (256, 256), (300, 200), (1030, 40), (2048, 70)]
 
 
 @pytest.mark.parametrize("m,n", FP64_SHAPES)

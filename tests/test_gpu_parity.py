@@ -268,11 +268,13 @@ def test_scaling_and_real_symmetries_bitwise(prec):
 
 
 def test_resident_schedule_applies_where_documented():
-    """The single-launch schedule is taken for dd with m <= 1024 and refused
-    (MGS_ERR_DIMS when it is required) for qd and for m > 1024."""
+    """The single-launch schedule is taken for dd with m <= 1024 and for
+    double with m <= 2048, and refused (MGS_ERR_DIMS when it is required)
+    for qd and beyond those rows."""
     from paper_1210_0800_amd import _lib
 
-    for prec, m, n, ok in ((2, 1024, 1024, True), (2, 300, 200, True), (2, 1100, 40, False), (4, 300, 200, False)):
+    for prec, m, n, ok in ((2, 1024, 1024, True), (2, 300, 200, True), (2, 1100, 40, False), (4, 300, 200, False),
+                           (1, 2048, 64, True), (1, 700, 500, True), (1, 2100, 20, False)):
         p = inputs.random_problem(prec, m, n, seed=m + n, config=58)
         if ok:
             f = api.mgs_qr(T(p["A"]), T(p["b"]), schedule="resident")
