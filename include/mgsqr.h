@@ -351,6 +351,18 @@ int mgs_newton_batched(int batch, int neq, int nvar, int nmon, int nvpm, int pre
                        const double *coef, double *x, int iters, double *dnorm, void *work, size_t work_bytes,
                        int *info, mgs_stream_t stream);
 
+/*
+ * mgs_set_jitter -- race checks (diagnostics, not for production use):
+ * with seed != 0, the kernels that synchronise across waves or workgroups
+ * (the single-launch factorisation, the one-workgroup and batched kernels,
+ * the triangular solves across workgroups) pause each wave for 0..15 x 64
+ * clocks at every step, the length drawn from (seed, workgroup, wave,
+ * step).  Every reduction order is fixed, so results must be bitwise those
+ * of seed 0; a difference is a race.  Applies to launches made after the
+ * call, process-wide, until called again with 0.
+ */
+void mgs_set_jitter(unsigned seed);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ MGS_MAX_ROWS = {1: 4096, 2: 4096, 4: 2048}
 
 EXPORTS = ("mgs_abi_version", "mgs_status_string", "mgs_workspace_size", "mgs_qr", "mgs_qr_schedule",
            "ls_solve", "ls_backsolve", "ls_adjoint", "mgs_refine_solve", "mgs_qr64", "mgs_lstsq_batched",
-           "mgs_qr_noalloc", "mgs_poly_eval", "mgs_newton_workspace_size", "mgs_newton_batched")
+           "mgs_qr_noalloc", "mgs_poly_eval", "mgs_newton_workspace_size", "mgs_newton_batched", "mgs_set_jitter")
 SCHEDULES = {"auto": 0, "panel": 1, "resident": 2, "small": 3}
 
 _lib = None
@@ -71,6 +71,8 @@ def lib():
         L.mgs_newton_workspace_size.restype = I
         L.mgs_newton_batched.argtypes = [I, I, I, I, I, I, P, P, P, P, I, P, P, S, P, P]
         L.mgs_newton_batched.restype = I
+        L.mgs_set_jitter.argtypes = [ctypes.c_uint]
+        L.mgs_set_jitter.restype = None
         _lib = L
     return _lib
 

@@ -301,6 +301,13 @@ def lstsq_batched(A, b=None, *, Q=None, R=None, y=None, x=None, rho=None, info=N
     return dict(Q=Q, R=R, y=y, x=x, rho=rho, info=info)
 
 
+def set_jitter(seed):
+    """Race checks (mgs_set_jitter): seed != 0 adds pseudo-random pauses to
+    the kernels that synchronise across waves or workgroups; results must
+    stay bitwise the same.  0 switches it off."""
+    _lib.lib().mgs_set_jitter(int(seed) & 0xFFFFFFFF)
+
+
 class PolySystem:
     """A polynomial system on the card (Section 7: transferred once):
     vars, exps int32 [neq, nmon, nvpm], coef float64 [prec, 2, neq, nmon]

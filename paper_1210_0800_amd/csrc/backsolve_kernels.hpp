@@ -81,7 +81,7 @@ template <class P, bool FWD>
 __global__ __launch_bounds__(BP_ROWS) void trsv_pipe_kernel(int n, const double *R, int ldr, size_t planeR,
                                                             const double *y, size_t planeY, double *x, int *info,
                                                             const int *skip, long long spin_ticks,
-                                                            long long *trace) {
+                                                            long long *trace, unsigned jitter) {
   if (skip != nullptr && *skip != 0) return;
   using C = typename P::C;
   using Rl = typename P::R;
@@ -183,6 +183,7 @@ __global__ __launch_bounds__(BP_ROWS) void trsv_pipe_kernel(int n, const double 
     fetch(s0, ra0, xa0);
 #pragma unroll 1
     for (int k = 0; k < nch; k += 2) {
+      res_jitter(jitter, (unsigned)k);
       fetch(s0 + CH, ra1, xa1);
       if (!consume(s0, ra0, xa0)) return;
       s0 += CH;
@@ -209,6 +210,7 @@ __global__ __launch_bounds__(BP_ROWS) void trsv_pipe_kernel(int n, const double 
   int cc = c2;
 #pragma unroll 1
   for (int rd = 0; rd < rounds2; ++rd) {
+    res_jitter(jitter, 0x10000u + (unsigned)rd);
 #pragma unroll
     for (int t = 0; t < BP_RING; ++t) {
       const int k = cc - r0;  // lane of row cc (outside [0, 64) past the block)

@@ -42,6 +42,7 @@ struct BatArgs {
   double *rho;  // [batch][L] or null
   int *info;    // [batch]
   long long spin_ticks;
+  unsigned jitter;  // race checks: seed of the timing jitter (0: none)
 };
 
 // Lane 63's accumulator, wave-uniform.
@@ -153,6 +154,7 @@ __global__ __launch_bounds__(64 * NW) void mgs_batched_kernel(BatArgs a) {
   if (w == 0) normalise(0, q);
   const int lastj = w < a.ncols ? w + NW * ((a.ncols - 1 - w) / NW) : -1;  // this wave's last column
   for (int k = 0; k < n && k < lastj; ++k) {
+    res_jitter(a.jitter, (unsigned)k);
     if (k % NW != w) {
       const long long t0 = wall_clock64();
       while (__hip_atomic_load(&flag[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) {

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <atomic>
 #include <mutex>
 
 #include "adjoint_kernels.hpp"
@@ -157,6 +158,10 @@ struct DevInfo {
 };
 bool dev_info(DevInfo &d);
 
+// Race checks: the timing-jitter seed handed to the kernels that
+// synchronise across waves or workgroups (mgs_set_jitter; 0: none).
+std::atomic<unsigned> g_jitter{0};
+
 // Back substitution across workgroups (one wave per 64 rows, cooperative);
 // returns 1 when it does not apply (one block only, or the workgroups
 // cannot all be resident), so that the caller takes the one-workgroup
@@ -182,7 +187,8 @@ int backsolve_pipe_launch(int n, const double *R, int ldr, size_t planeR, const 
 #else
   long long *trace = nullptr;
 #endif
-  void *args[] = {&n, &R, &ldr, &planeR, &y, &planeY, &x, &info, &skip, &spin, &trace};
+  unsigned jitter = g_jitter.load(std::memory_order_relaxed);
+  void *args[] = {&n, &R, &ldr, &planeR, &y, &planeY, &x, &info, &skip, &spin, &trace, &jitter};
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G), dim3(BP_ROWS), args, 0, st) !=
       hipSuccess) {
     (void)hipGetLastError();
@@ -588,6 +594,7 @@ int res_launch(const StepArgs &s, void *sync, double *u, hipStream_t st) {
   a.spin_ticks = d.wclk_khz * 2000;  // 2 s
   a.kbase = s.kbase;
   a.init_info = s.init_info;
+  a.jitter = g_jitter.load(std::memory_order_relaxed);
 #ifdef MGS_TRACE
   a.trace = g_trace;
 #endif
@@ -628,6 +635,7 @@ int small_launch_dd(const StepArgs &s, hipStream_t st) {
   a.rho = s.rho;
   a.info = s.info;
   a.spin_ticks = d.wclk_khz * 2000;  // 2 s
+  a.jitter = g_jitter.load(std::memory_order_relaxed);
   hipLaunchKernelGGL(mgs_small_kernel, dim3(1), dim3(64 * SMALL_WAVES), 0, st, a);
   return hipGetLastError() == hipSuccess ? MGS_OK : MGS_ERR_LAUNCH;
 }
@@ -731,6 +739,7 @@ int newton_launch(int batch, int neq, int nvar, int nmon, int nvpm, const int *v
     a.rho = nullptr;
     a.info = info;
     a.spin_ticks = spin;
+    a.jitter = g_jitter.load(std::memory_order_relaxed);
     const int rc = batched_dispatch(P::L, a, st);
     if (rc != MGS_OK) return rc;
     hipLaunchKernelGGL((newton_update_kernel<P>), dim3(batch), dim3(64), 0, st, nvar, x, w.d, info,
@@ -743,6 +752,9 @@ int newton_launch(int batch, int neq, int nvar, int nmon, int nvpm, const int *v
 }  // namespace
 
 extern "C" {
+
+void mgs_set_jitter(unsigned seed) { g_jitter.store(seed, std::memory_order_relaxed); }
+
 
 #ifdef MGS_TRACE
 // Diagnostic builds only (not declared in the public header).
@@ -842,6 +854,7 @@ int mgs_qr_schedule(int m, int n, int prec, const double *A, int lda, double *Q,
         ba.rho = a.rho;
         ba.info = info;
         ba.spin_ticks = d.wclk_khz * 2000;  // 2 s
+        ba.jitter = g_jitter.load(std::memory_order_relaxed);
         rc = batched_dispatch(prec, ba, st);
       }
     }
@@ -1056,6 +1069,7 @@ int mgs_lstsq_batched(int batch, int m, int n, int prec, const double *A, int ld
   a.rho = b ? rho : nullptr;
   a.info = info;
   a.spin_ticks = d.wclk_khz * 2000;  // 2 s
+  a.jitter = g_jitter.load(std::memory_order_relaxed);
   return batched_dispatch(prec, a, reinterpret_cast<hipStream_t>(stream));
 }
 

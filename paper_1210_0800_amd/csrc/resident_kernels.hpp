@@ -67,6 +67,7 @@ struct ResArgs {
   unsigned int *sync;  // RES_SYNC_WORDS words, zero at launch: per-wave counters and the abort flag
   int bw, np, G;  // bw must be 1: every panel is one column
   int xcd_group;        // logical workgroups per XCD (G / 8), 0 for identity numbering
+  unsigned jitter;      // race checks: seed of the timing jitter (0: none)
   int kbase;            // column offset of this matrix in the caller's, for info
   int init_info;        // clear info at the start (else keep an earlier status)
   int defer;            // look-ahead window of the critical-path-first rule (columns, >= 1)
@@ -197,6 +198,21 @@ __device__ __forceinline__ void info_first_bad(int *info, int v) {
     if (prev == old) break;
     old = prev;
   }
+}
+
+// Race checks: with seed != 0, a pause of 0..15 x 64 clocks, the same for
+// the whole wave, drawn from (seed, workgroup, wave, step) by an integer
+// hash.  Results must not change: every reduction order is fixed, so a
+// difference under jitter is a race.  seed 0 (the default) costs one
+// scalar compare.
+__device__ __forceinline__ void res_jitter(unsigned seed, unsigned step) {
+  if (seed == 0) return;
+  unsigned h = seed * 0x9E3779B1u ^ blockIdx.x * 0x85EBCA77u ^ (threadIdx.x >> 6) * 0xC2B2AE3Du ^ step * 0x27D4EB2Fu;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  const int n = __builtin_amdgcn_readfirstlane((int)(h & 15u));
+  for (int i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(1);
 }
 
 // Common end of a bounded wait: true (and the abort flag set, info
@@ -716,7 +732,9 @@ struct Resident {
     // Each pass performs one bulk projection (apply), one look-ahead
     // projection or one normalisation; each has a single call site so that
     // the loop body holds one copy of it.
+    unsigned pass = 0;
     while (true) {
+      res_jitter(a.jitter, pass++);
       int mode = 0;  // 1 apply, 2 lookahead_step, 3 own_norm
       int opk = -1, lo = 0;
       int qsrc = 3;  // q_opk: 0 wait and load from Q, 1 owned column, 2 load from Q (already seen), 3 none, 4 poll U

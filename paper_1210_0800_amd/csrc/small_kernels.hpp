@@ -38,6 +38,7 @@ struct SmallArgs {
   double *rho;
   int *info;
   long long spin_ticks;  // wall-clock limit of one wait
+  unsigned jitter;       // race checks: seed of the timing jitter (0: none)
 };
 
 __device__ __forceinline__ PrecDD::Acc small_lane63(const PrecDD::Acc &v) {
@@ -130,6 +131,7 @@ __global__ __launch_bounds__(64 * SMALL_WAVES) void mgs_small_kernel(SmallArgs a
   C q = P::czero();
   if (w == 0 && a.n > 0) normalise(0, q);
   for (int k = 0; k < a.n; ++k) {
+    res_jitter(a.jitter, (unsigned)k);
     // this wave's last column; nothing left to do once it is <= k
     const int lastj = w + SMALL_WAVES * ((a.ncols - 1 - w) / SMALL_WAVES);
     if (w >= a.ncols || lastj <= k) break;

@@ -1,0 +1,81 @@
+"""Determinism under timing jitter (race checks): every kernel that
+synchronises across waves or workgroups fixes its reduction order, so its
+results must be bitwise the same when each wave is delayed at every step by
+a pseudo-random pause (mgs_set_jitter).  A difference would be a race.
+Covered: the single-launch factorisation (dd 1024 x 1024 + b, FP64
+700 x 500 + b), the triangular solve across workgroups (n = 1024), the
+one-workgroup dd kernel (32 x 32), the batched kernel (64 systems), and the
+FP64 panels of the precision form's factorisation (mgs_qr64, 512 x 200).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1210_0800_amd import api, inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+SEEDS = (1, 2, 0xDEADBEEF)
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def same(ref, out):
+    for k, v in ref.items():
+        if isinstance(v, torch.Tensor):
+            assert torch.equal(v, out[k]), k
+
+
+def under_jitter(run):
+    api.set_jitter(0)
+    ref = run()
+    torch.cuda.synchronize()
+    try:
+        for seed in SEEDS:
+            api.set_jitter(seed)
+            out = run()
+            torch.cuda.synchronize()
+            same(ref, out)
+    finally:
+        api.set_jitter(0)
+    return ref
+
+
+def test_resident_dd_and_backsolve_bitwise_under_jitter():
+    d = inputs.config3(0)
+    A, b = T(d["A"]), T(d["b"])
+
+    def run():
+        f = api.mgs_qr(A, b)
+        x, info = api.ls_backsolve(f["R"], f["y"])
+        return dict(Q=f["Q"], R=f["R"], y=f["y"], rho=f["rho"], info=f["info"], x=x, info_bs=info)
+
+    ref = under_jitter(run)
+    assert int(ref["info"].item()) == 0 and int(ref["info_bs"].item()) == 0
+
+
+def test_resident_fp64_bitwise_under_jitter():
+    p = inputs.random_problem(1, 700, 500, seed=3, config=91)
+    A, b = T(p["A"]), T(p["b"])
+    ref = under_jitter(lambda: api.mgs_qr(A, b))
+    assert int(ref["info"].item()) == 0
+
+
+def test_small_and_batched_bitwise_under_jitter():
+    d = inputs.config1()
+    A, b = T(d["A"]), T(d["b"])
+    ref = under_jitter(lambda: api.mgs_qr(A, b))
+    assert int(ref["info"].item()) == 0
+    bt = inputs.config1_batch(64, workers=4)
+    Ab, bb = T(bt["A"]), T(bt["b"])
+    ref = under_jitter(lambda: api.lstsq_batched(Ab, bb, with_y=True, with_rho=True))
+    assert int((ref["info"] != 0).sum().item()) == 0
+
+
+def test_precision_form_panels_bitwise_under_jitter():
+    p = inputs.random_problem(1, 512, 200, seed=5, config=92)
+    A, b = T(p["A"][0]), T(p["b"][0])
+    ref = under_jitter(lambda: api.mgs_qr64(A, b))
+    assert int(ref["info"].item()) == 0
