@@ -26,3 +26,27 @@ def test_config4_rhs_is_the_exact_product_rounded_to_qd():
         im = sum(F(A[0, 0, j, i]) * F(x[0, 1, j]) + F(A[0, 1, j, i]) * F(x[0, 0, j]) for j in range(48))
         assert abs(float(fval(b[:, 0, i]) - re)) <= 2.0 ** -210 * abs(float(re))
         assert abs(float(fval(b[:, 1, i]) - im)) <= 2.0 ** -210 * abs(float(im))
+
+
+def test_polysys_shape_seeding_and_root():
+    s = inputs.polysys(system=5)
+    t = inputs.polysys(system=5)
+    for k in ("vars", "exps", "coef", "root"):
+        assert np.array_equal(s[k], t[k]), k
+    neq, nmon, nvpm = s["vars"].shape
+    assert (neq, nmon, nvpm) == (32, 32, 5) and s["nvar"] == 32
+    # distinct variables per monomial, degrees 1..5
+    assert all(len(set(s["vars"][e, m])) == nvpm for e in range(neq) for m in range(nmon))
+    assert s["exps"].min() >= 1 and s["exps"].max() <= 5
+    # root entries are powers of i
+    r = s["root"][0, 0] + 1j * s["root"][0, 1]
+    assert np.all(np.isin(np.round(r), [1, -1, 1j, -1j])) and np.all(np.abs(r) == 1)
+    # coefficients: dyadic (k / 64) except the first of each equation, set
+    # so that f(x*) = 0; all of them exact in FP64, no lower limbs
+    c = s["coef"]
+    assert np.all(c[1:] == 0)
+    assert np.all(c[0, :, :, 1:] * 64 == np.round(c[0, :, :, 1:] * 64))
+    # the start point is the root plus a perturbation of the given size
+    x0 = inputs.near_root(s, 1e-3, system=5)
+    d = x0[0] - s["root"][0]
+    assert 0 < np.max(np.abs(d)) <= 1e-3 and np.all(x0[1:] == 0)
