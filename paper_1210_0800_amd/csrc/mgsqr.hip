@@ -49,21 +49,28 @@ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 struct Shape {
   int tw, rpt, rp;
 };
-Shape choose_shape(int m, int prec) {
+Shape choose_shape(int m, int prec, int ncols = 0) {
   const int rpt_max = prec == 1 ? 32 : (prec == 2 ? 16 : 8);
   Shape s;
   s.tw = pow2_at_least(ceil_div(m, 64 * rpt_max));
+  // qd with few columns: up to 4 waves per trailing column, so that the
+  // trailing columns of a launch give about 1024 waves (4 per compute unit)
+  // and each wave's share of a projection stays short.
+  if (prec == 4)
+    while (s.tw < 4 && ncols * s.tw < 1024) s.tw *= 2;
   s.rpt = pow2_at_least(ceil_div(m, 64 * s.tw));
   s.rp = s.rpt * s.tw / NWAVE > 1 ? s.rpt * s.tw / NWAVE : 1;
   return s;
 }
 constexpr int bw_for(int L, int RP) {
-  // complex elements per thread held by the panel role: FP64 16, dd 8,
-  // qd 4; the panel width is capped (FP64 / dd 4, qd 2) so that its loops
-  // unroll fully and every register array keeps static indices.
+  // complex elements per thread held by the panel role: FP64 16, dd 8;
+  // the panel width is capped (FP64 / dd 4) so that its loops unroll fully
+  // and every register array keeps static indices.  qd: one column per
+  // panel (the panel role's qd arithmetic is the serial part of each
+  // launch, and its look-ahead work grows with the square of the width).
   return L == 1 ? (16 / RP >= 4 ? 4 : (16 / RP >= 1 ? 16 / RP : 1))
                 : L == 2 ? (8 / RP >= 4 ? 4 : (8 / RP >= 1 ? 8 / RP : 1))
-                         : (4 / RP >= 2 ? 2 : (4 / RP >= 1 ? 4 / RP : 1));
+                         : 1;
 }
 
 // LDS budget for staged q vectors (gfx950: 160 KiB per CU).
@@ -139,8 +146,13 @@ int dispatch_shape(const StepArgs &a, const Shape &sh, hipStream_t st) {
       }
     } else if (sh.rpt == 8 && sh.tw == 2) {
       return launch_steps<P, 8, 2>(a, st);
-    } else if (sh.rpt == 8 && sh.tw == 4) {
-      return launch_steps<P, 8, 4>(a, st);
+    } else if (sh.tw == 4) {
+      switch (sh.rpt) {
+        case 1: return launch_steps<P, 1, 4>(a, st);
+        case 2: return launch_steps<P, 2, 4>(a, st);
+        case 4: return launch_steps<P, 4, 4>(a, st);
+        case 8: return launch_steps<P, 8, 4>(a, st);
+      }
     }
   }
   return MGS_ERR_DIMS;
@@ -805,7 +817,7 @@ int mgs_qr_schedule(int m, int n, int prec, const double *A, int lda, double *Q,
   if (!aligned8(work)) return MGS_ERR_POINTER;
   if (b && (!aligned8(b) || !aligned8(y))) return MGS_ERR_POINTER;
   if (work_bytes < qr_work_bytes(m, n, prec)) return MGS_ERR_WORKSPACE;
-  Shape sh = choose_shape(m, prec);
+  Shape sh = choose_shape(m, prec, n + (b ? 1 : 0));
   StepArgs a;
   a.m = m;
   a.n = n;
