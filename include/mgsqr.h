@@ -104,10 +104,11 @@ int mgs_workspace_size(int m, int n, int prec, int op, size_t *bytes);
  *             m n bytes).
  *   info      device int, see above.
  * prec 1, 2 or 4.  Requires 1 <= n <= m <= MGS_MAX_ROWS_{DD,QD}.
- * Schedule: with m <= 64 and at most 64 columns of [A b] (and, in qd, the
- * q vectors within 159 KiB: 64 m n bytes), one workgroup (a column per wave
- * slot, q vectors through LDS; for double and qd the kernel of
- * mgs_lstsq_batched on one system); in dd and double when
+ * Schedule: in dd and double with m <= 64 and at most 64 columns of [A b],
+ * one workgroup (a column per wave slot, q vectors through LDS; for double
+ * the kernel of mgs_lstsq_batched on one system; qd takes it only when
+ * mgs_qr_schedule asks for it, within 159 KiB of q vectors: 64 m n bytes);
+ * in dd and double when
  * every column fits in the register file of the device (dd: m <= 1024 and
  * at most 5 columns per compute unit, 8 when m <= 512, e.g. 1024 x 1024
  * with b on 256 compute units; double: m <= 2048, 5 columns per compute

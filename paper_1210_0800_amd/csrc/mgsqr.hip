@@ -845,8 +845,11 @@ int mgs_qr_schedule(int m, int n, int prec, const double *A, int lda, double *Q,
     int rc = 1;
     if (prec == 2) {
       rc = small_launch_dd(a, st);
-    } else if (batched_fits(m, n, a.ncols, prec)) {
-      // FP64 and qd: the batched kernel on a batch of one.
+    } else if (batched_fits(m, n, a.ncols, prec) && (prec == 1 || mode == MGS_SCHED_SMALL)) {
+      // FP64 (and qd when asked for): the batched kernel on a batch of
+      // one.  A single qd system takes the per-panel schedule by default:
+      // the batched kernel's qd instantiation holds 16 waves per system and
+      // spills to scratch (0.94 ms for 32 x 32 against ~0.5 ms).
       DevInfo d;
       if (dev_info(d)) {
         BatArgs ba;
