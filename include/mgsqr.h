@@ -325,7 +325,9 @@ int mgs_poly_eval(int batch, int neq, int nvar, int nmon, int nvpm, int prec, co
 
 /*
  * mgs_newton_workspace_size -- bytes of device workspace mgs_newton_batched
- * needs (J, -f, R and the correction of every point).
+ * needs (J, -f, R and the correction of every point; for a single point in
+ * dd or qd also Q^H b, a status word and the workspace of mgs_qr's
+ * single-system schedule).
  */
 int mgs_newton_workspace_size(int batch, int neq, int nvar, int prec, size_t *bytes);
 
@@ -334,7 +336,9 @@ int mgs_newton_workspace_size(int batch, int neq, int nvar, int prec, size_t *by
  * the card: per step, f and J by mgs_poly_eval's kernel, the correction d
  * as the least-squares solution of J d = -f by the MGS of Figure 1 on
  * [J -f] (Equation (1)) and the back substitution of Figure 3 (the
- * mgs_lstsq_batched kernel, one workgroup per point), then x += d.
+ * mgs_lstsq_batched kernel, one workgroup per point; for a single point in
+ * dd or qd the single-system schedules of mgs_qr and ls_backsolve), then
+ * x += d.
  *   Requires nvar <= neq <= 64 and 16 prec neq nvar <= 162816 (the MGS
  *   limits of mgs_lstsq_batched), iters >= 0.
  *   x     [in/out] the points (updated in place).

@@ -701,9 +701,13 @@ void *scratch_address() {
 }
 
 // Newton: J (batch systems of neq x nvar), b (batch x neq), R (batch x
-// nvar x nvar), d (batch x nvar), each in the working precision.
+// nvar x nvar), d (batch x nvar), each in the working precision; for one
+// point in dd or qd also y (nvar), an int and the workspace of mgs_qr.
 struct NewtonWork {
-  double *A, *b, *R, *d;
+  double *A, *b, *R, *d, *y;
+  int *info2;
+  void *qrw;
+  size_t qrw_bytes;
   size_t bytes;
 };
 NewtonWork newton_layout(int batch, int neq, int nvar, int prec, void *base) {
@@ -719,6 +723,16 @@ NewtonWork newton_layout(int batch, int neq, int nvar, int prec, void *base) {
   w.b = take(B * NP * neq);
   w.R = take(B * NP * nvar * nvar);
   w.d = take(B * NP * nvar);
+  w.y = nullptr;
+  w.info2 = nullptr;
+  w.qrw = nullptr;
+  w.qrw_bytes = 0;
+  if (batch == 1 && prec >= 2) {
+    w.y = take(NP * nvar);
+    w.info2 = reinterpret_cast<int *>(take(1));
+    w.qrw_bytes = qr_work_bytes(neq, nvar, prec);
+    w.qrw = take((w.qrw_bytes + sizeof(double) - 1) / sizeof(double));
+  }
   w.bytes = off;
   return w;
 }
@@ -734,6 +748,21 @@ int newton_launch(int batch, int neq, int nvar, int nmon, int nvpm, const int *v
     hipLaunchKernelGGL((poly_eval_kernel<P>), dim3(neq, batch), dim3(64), 0, st, neq, nvar, nmon, nvpm, vars, exps,
                        coef, x, w.A, w.b, true);
     if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
+    if (w.qrw != nullptr) {
+      // One point (dd, qd): the single-system schedules of mgs_qr (dd: one
+      // workgroup of 16 waves; qd: one column per launch), quicker than a
+      // batch of one, then the back substitution (its own status word: a
+      // zero pivot is already reported by the factorisation).
+      int rc = mgs_qr_schedule(neq, nvar, P::L, w.A, neq, w.A, neq, w.R, nvar, w.b, w.y, nullptr, w.qrw, w.qrw_bytes,
+                               info, MGS_SCHED_AUTO, reinterpret_cast<mgs_stream_t>(st));
+      if (rc != MGS_OK) return rc;
+      rc = backsolve_launch<P>(nvar, w.R, nvar, w.y, w.d, w.info2, st);
+      if (rc != MGS_OK) return rc;
+      hipLaunchKernelGGL((newton_update_kernel<P>), dim3(batch), dim3(64), 0, st, nvar, x, w.d, info,
+                         dnorm != nullptr ? dnorm + (size_t)k * batch : nullptr);
+      if (hipGetLastError() != hipSuccess) return MGS_ERR_LAUNCH;
+      continue;
+    }
     BatArgs a;
     a.batch = batch;
     a.m = neq;

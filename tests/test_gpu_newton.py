@@ -134,16 +134,39 @@ def test_newton_overdetermined():
 
 
 def test_points_are_independent():
+    # one workgroup per point: a point's iterates do not depend on the batch
+    # (bitwise); a single point takes the single-system schedules instead
     L = 2
     s = make(L, system=2)
     X0 = starts(s, L, 9)
     ds = dev_system(s)
     xa = T(X0)
     api.newton_batched(ds, xa, 3)
-    xb = T(X0[4:5])
+    xb = T(X0[4:6])
     api.newton_batched(ds, xb, 3)
     torch.cuda.synchronize()
-    assert torch.equal(xa[4:5], xb)
+    assert torch.equal(xa[4:6], xb)
+
+
+@pytest.mark.parametrize("L,iters", [(2, 6), (4, 7)])
+def test_single_point_matches_the_oracle(L, iters):
+    # batch of one in dd / qd: mgs_qr's single-system schedules and the back
+    # substitution in place of the batched kernel
+    s = make(L, system=1)
+    X0 = starts(s, L, 1)
+    ds = dev_system(s)
+    for k in (1, 2):
+        x = T(X0)
+        r = api.newton_batched(ds, x, k)
+        torch.cuda.synchronize()
+        assert int(r["info"].item()) == 0
+        xo, dno = oracle.newton(s, X0[0], k)
+        assert np.sqrt(np.sum(diff(x.cpu().numpy()[0], xo) ** 2)) <= 1e3 * eval_tol(L)
+        np.testing.assert_allclose(r["dnorm"].cpu().numpy()[:, 0], dno, rtol=1e-12)
+    x = T(X0)
+    api.newton_batched(ds, x, iters)
+    torch.cuda.synchronize()
+    assert np.sqrt(np.sum(diff(x.cpu().numpy()[0], _at(s["root"], L)) ** 2)) <= FLOOR[L]
 
 
 def test_singular_jacobian_keeps_the_point():
