@@ -40,11 +40,26 @@ F_DD = dict(cmulc=60, upd=66, abs2=28, scale=20, merge=16)
 # with b), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this
 # benchmark, each scaled by the same counter on a device copy of known size
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0; see profiles/).  Valid only for the
-# kernel and launch sources they were taken on (hash below); reported as
-# null otherwise.
+# kernel sources and the launch code they were taken on (hash below: the
+# kernel headers whole, of mgsqr.hip the part that plans and launches the
+# single-launch factorisation); reported as null otherwise.
 TRAFFIC = dict(fetch_bytes=2.0 * 159682.8 * 1024, write_bytes=169424.9 * 1024, sources="8409072dc32ce286")
 KERNEL_SOURCES = ["paper_1210_0800_amd/csrc/resident_kernels.hpp", "paper_1210_0800_amd/csrc/ddqd.hpp",
-                  "paper_1210_0800_amd/csrc/mgs_kernels.hpp", "paper_1210_0800_amd/csrc/mgsqr.hip"]
+                  "paper_1210_0800_amd/csrc/mgs_kernels.hpp",
+                  ("paper_1210_0800_amd/csrc/mgsqr.hip", "// Columns held by the workgroup holding the most",
+                   "// dd systems of at most SMALL_MAX_ROWS")]
+
+
+def _source_part(entry):
+    if isinstance(entry, str):
+        with open(os.path.join(ROOT, entry), "rb") as fh:
+            return fh.read()
+    path, start, end = entry
+    with open(os.path.join(ROOT, path), "rb") as fh:
+        text = fh.read()
+    i = text.find(start.encode())
+    j = text.find(end.encode(), i + 1)
+    return text[i:j] if 0 <= i < j else text
 
 
 def traffic_bytes():
@@ -52,8 +67,7 @@ def traffic_bytes():
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        h.update(_source_part(f))
     if h.hexdigest()[:16] != TRAFFIC["sources"]:
         return None
     return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
