@@ -416,10 +416,10 @@ struct Resident {
 
   // Block sums on the critical path (the steps that factor a panel), with a
   // single barrier: each wave scans its own partial (DPP), lane 63 stores
-  // the wave total, and after the barrier every thread merges the NW wave
-  // totals in the same fixed pairwise tree, so all threads hold the same
-  // sum.  Two buffers alternate: a wave can only overwrite one after every
-  // wave has passed the next barrier, i.e. finished reading it.
+  // the wave total, and after the barrier every wave merges the NW wave
+  // totals in the same fixed pairwise tree (xch_sum), so all threads hold
+  // the same sum.  Two buffers alternate: a wave can only overwrite one
+  // after every wave has passed the next barrier, i.e. finished reading it.
   __device__ __forceinline__ void xch_put(int pos, Acc t, bool re_only) {
     wave_sum_any<P>(t, re_only);
     if (lane == 63) {
@@ -428,23 +428,24 @@ struct Resident {
       for (int c = 0; c < NA; ++c) xch[xb][pos][c][wave] = d[c];
     }
   }
-  template <int W0, int CNT>
-  __device__ __forceinline__ Acc xch_tree(int pos, bool re_only) const {
-    if constexpr (CNT == 1) {
-      Acc u;
-      double *du = reinterpret_cast<double *>(&u);
+  // The merge of the NW wave totals, spread over the lanes: lane l starts
+  // from the total of wave l mod NW and log2(NW) butterfly steps merge it
+  // with the lane l^1, l^2, l^4 (DPP inside rows of 16 lanes, where the
+  // totals repeat with period NW, so that a rotation by 4 reaches the l^4
+  // partner's value).  The accumulator merge gives the same bits in either
+  // operand order (TwoSum's error term is exact), so every lane ends with
+  // the pairwise tree ((w0 w1)(w2 w3))((w4 w5)(w6 w7)), in 3 merges per
+  // lane instead of 7 one after another.
+  __device__ __forceinline__ Acc xch_sum(int pos, bool re_only) const {
+    static_assert(NW == 1 || NW == 2 || NW == 4 || NW == 8, "butterfly over at most 8 waves");
+    Acc x;
+    double *dx = reinterpret_cast<double *>(&x);
 #pragma unroll
-      for (int c = 0; c < NA; ++c) du[c] = xch[xb][pos][c][W0];
-      return u;
-    } else {
-      Acc x = xch_tree<W0, CNT / 2>(pos, re_only);
-      const Acc y = xch_tree<W0 + CNT / 2, CNT / 2>(pos, re_only);
-      if (re_only)
-        P::acc_merge_re(x, y);
-      else
-        P::acc_merge(x, y);
-      return x;
-    }
+    for (int c = 0; c < NA; ++c) dx[c] = xch[xb][pos][c][lane & (NW - 1)];
+    if constexpr (NW >= 2) dpp_step_any<P, 0xB1, 0xf>(x, re_only);   // quad_perm [1,0,3,2]: lane l^1
+    if constexpr (NW >= 4) dpp_step_any<P, 0x4E, 0xf>(x, re_only);   // quad_perm [2,3,0,1]: lane l^2
+    if constexpr (NW >= 8) dpp_step_any<P, 0x124, 0xf>(x, re_only);  // row_ror:4: lane l+-4 within the row
+    return x;
   }
 
   // Publication of q_k: this wave's device-scope stores of its rows are
@@ -496,7 +497,7 @@ struct Resident {
     });
     xch_put(0, nacc, true);
     lds_barrier();
-    const Rl s2 = P::acc_value_re(xch_tree<0, NW>(0, true));
+    const Rl s2 = P::acc_value_re(xch_sum(0, true));
     xb ^= 1;
     if (!P::ok_norm(s2) && tid == 0) info_first_bad(a.info, a.kbase + x + 1);
     Rl rkk, inv;
@@ -556,8 +557,8 @@ struct Resident {
     if (last) RES_TRACE_LAST(ps, 8);
     lds_barrier();
     if (last) RES_TRACE(ps, 5);
-    const Rl s2 = P::acc_value_re(xch_tree<0, NW>(1, true));
-    const C d = P::acc_value(xch_tree<0, NW>(0, false));
+    const Rl s2 = P::acc_value_re(xch_sum(1, true));
+    const C d = P::acc_value(xch_sum(0, false));
     xb ^= 1;
     Rl rkk, inv;
     root_and_inverse<P>(s2, rkk, inv);
