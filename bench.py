@@ -41,11 +41,12 @@ F_DD = dict(cmulc=60, upd=66, abs2=28, scale=20, merge=16)
 # benchmark, each scaled by the same counter on a device copy of known size
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0; see profiles/).  Valid only for the
 # kernel sources and the launch code they were taken on (hash below: the
-# kernel headers whole, of mgsqr.hip the part that plans and launches the
-# single-launch factorisation); reported as null otherwise.
-TRAFFIC = dict(fetch_bytes=2.0 * 159682.8 * 1024, write_bytes=169424.9 * 1024, sources="8409072dc32ce286")
+# kernel's header and the arithmetic whole, of mgs_kernels.hpp the helpers
+# it uses, of mgsqr.hip the part that plans and launches the single-launch
+# factorisation); reported as null otherwise.
+TRAFFIC = dict(fetch_bytes=2.0 * 1.595e5 * 1024, write_bytes=1.687e5 * 1024, sources="ca482b15ed16f48f")
 KERNEL_SOURCES = ["paper_1210_0800_amd/csrc/resident_kernels.hpp", "paper_1210_0800_amd/csrc/ddqd.hpp",
-                  "paper_1210_0800_amd/csrc/mgs_kernels.hpp",
+                  ("paper_1210_0800_amd/csrc/mgs_kernels.hpp", "// MGS QR, least-squares", "struct StepArgs {"),
                   ("paper_1210_0800_amd/csrc/mgsqr.hip", "// Columns held by the workgroup holding the most",
                    "// dd systems of at most SMALL_MAX_ROWS")]
 
