@@ -41,9 +41,12 @@ __device__ __forceinline__ typename P::C nt_pow(const typename P::C &b, int d) {
 // c prod_t x_t^{d_t} and its derivatives c d_t x_t^{d_t - 1} prod_{u != t}
 // x_u^{d_u} (prefix and suffix products) are formed in the working
 // precision; f_e is a wave sum (DPP, fixed tree), and each Jacobian entry
-// J(e, j) the sum, in monomial order, of the derivatives by x_j (the lane of
-// variable j gathers them from LDS).  f_e (-f_e when negate) goes to b, J
-// to A, both in the batched least-squares layout.
+// J(e, j) the sum, in monomial order, of the derivatives by x_j: the
+// derivative entries are listed by variable (stable, so each list is in
+// monomial order: counts, their prefix sum over the lanes, then a fill),
+// and the lane of variable j merges its list from LDS, all lanes at once,
+// in as many rounds as the longest list.  f_e (-f_e when negate) goes to
+// b, J to A, both in the batched least-squares layout.
 template <class P>
 __global__ __launch_bounds__(64) void poly_eval_kernel(int neq, int nvar, int nmon, int nvpm, const int *vars,
                                                        const int *exps, const double *coef, const double *x,
@@ -54,6 +57,7 @@ __global__ __launch_bounds__(64) void poly_eval_kernel(int neq, int nvar, int nm
   __shared__ double xs[NP][NT_MAX_VARS];                       // the point
   __shared__ double ds[NP][NT_MAX_MON * NT_MAX_VPM];           // derivatives [m * nvpm + t]
   __shared__ int vs[NT_MAX_MON * NT_MAX_VPM];                  // their variables
+  __shared__ int by_var[NT_MAX_MON * NT_MAX_VPM];              // entries listed by variable
   const int lane = threadIdx.x;
   const int e = blockIdx.x, s = blockIdx.y;
   const double *xp = x + (size_t)s * NP * nvar;
@@ -116,17 +120,38 @@ __global__ __launch_bounds__(64) void poly_eval_kernel(int neq, int nvar, int nm
   double *bp = b + (size_t)s * NP * neq;
   if (lane == 0) P::store(bp + e, (size_t)neq, negate ? P::cneg(fe) : fe);
   __syncthreads();
-  // J(e, j) for j = lane
-  if (lane < nvar) {
-    Acc aj;
-    P::acc_zero(aj);
-    for (int k = 0; k < nmon * nvpm; ++k) {
-      if (vs[k] == lane) {
-        Acc d1;
-        P::acc_set(d1, P::load(&ds[0][k], (size_t)NT_MAX_MON * NT_MAX_VPM));
-        P::acc_merge(aj, d1);
-      }
+  // J(e, j) for j = lane.  The entries of variable `lane`, in ascending
+  // order, go to by_var[off, off + cnt).
+  const int nent = nmon * nvpm;
+  int cnt = 0;
+  for (int k = 0; k < nent; ++k) cnt += vs[k] == lane ? 1 : 0;
+  int off = cnt;  // inclusive scan over the lanes, then exclusive
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(off, d);
+    if (lane >= d) off += o;
+  }
+  off -= cnt;
+  {
+    int w = off;
+    for (int k = 0; k < nent; ++k) {
+      if (vs[k] == lane) by_var[w++] = k;
     }
+  }
+  int rounds = cnt;
+#pragma unroll
+  for (int mask = 32; mask >= 1; mask >>= 1) rounds = max(rounds, __shfl_xor(rounds, mask));
+  __syncthreads();
+  Acc aj;
+  P::acc_zero(aj);
+  for (int c = 0; c < rounds; ++c) {
+    if (c < cnt) {
+      Acc d1;
+      P::acc_set(d1, P::load(&ds[0][by_var[off + c]], (size_t)NT_MAX_MON * NT_MAX_VPM));
+      P::acc_merge(aj, d1);
+    }
+  }
+  if (lane < nvar) {
     double *ap = A + (size_t)s * NP * neq * nvar;
     P::store(ap + (size_t)lane * neq + e, (size_t)neq * nvar, P::acc_value(aj));
   }
