@@ -41,11 +41,14 @@ F_DD = dict(cmulc=60, upd=66, abs2=28, scale=20, merge=16)
 # benchmark, each scaled by the same counter on a device copy of known size
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0; see profiles/).  Valid only for the
 # kernel sources and the launch code they were taken on (hash below: the
-# kernel's header and the arithmetic whole, of mgs_kernels.hpp the helpers
-# it uses, of mgsqr.hip the part that plans and launches the single-launch
-# factorisation); reported as null otherwise.
-TRAFFIC = dict(fetch_bytes=2.0 * 1.595e5 * 1024, write_bytes=1.687e5 * 1024, sources="ca482b15ed16f48f")
-KERNEL_SOURCES = ["paper_1210_0800_amd/csrc/resident_kernels.hpp", "paper_1210_0800_amd/csrc/ddqd.hpp",
+# kernel's header whole, the dd and FP64 arithmetic and the precision
+# policies (not the qd functions, which it does not use), of mgs_kernels.hpp
+# the helpers it uses, of mgsqr.hip the part that plans and launches the
+# single-launch factorisation); reported as null otherwise.
+TRAFFIC = dict(fetch_bytes=2.0 * 1.595e5 * 1024, write_bytes=1.687e5 * 1024, sources="6b02a83aa1e85c44")
+KERNEL_SOURCES = ["paper_1210_0800_amd/csrc/resident_kernels.hpp",
+                  ("paper_1210_0800_amd/csrc/ddqd.hpp", "// Device arithmetic", "// " + "-" * 67 + " qd --"),
+                  ("paper_1210_0800_amd/csrc/ddqd.hpp", "// " + "-" * 57 + " precisions ----", None),
                   ("paper_1210_0800_amd/csrc/mgs_kernels.hpp", "// MGS QR, least-squares", "struct StepArgs {"),
                   ("paper_1210_0800_amd/csrc/mgsqr.hip", "// Columns held by the workgroup holding the most",
                    "// dd systems of at most SMALL_MAX_ROWS")]
@@ -59,7 +62,7 @@ def _source_part(entry):
     with open(os.path.join(ROOT, path), "rb") as fh:
         text = fh.read()
     i = text.find(start.encode())
-    j = text.find(end.encode(), i + 1)
+    j = len(text) if end is None else text.find(end.encode(), i + 1)
     return text[i:j] if 0 <= i < j else text
 
 
