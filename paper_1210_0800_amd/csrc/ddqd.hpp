@@ -200,19 +200,35 @@ __device__ __forceinline__ qd qd_recip(qd b) {
   }
   return x;
 }
-// sqrt(s) for s > 0: inverse square root y by two Newton iterations
-// y <- y + y (1 - s y^2) / 2 from the FP64 one (relative error about 2^-52,
-// then 2^-104, then 2^-206: each iteration squares it), then x = s y
+// Inverse square root of s > 0 to about 2^-103, as a dd: one Newton step
+// y + y (1 - s y^2) / 2 from the FP64 one, whose relative error (about
+// 2^-52) it squares.  The step only needs dd precision: s enters through
+// its two leading limbs, y^2 exactly (TwoProd), 1 - s y^2 is about 2^-52
+// (its leading difference exact by Sterbenz), so one FP64 product of it
+// with y is accurate to about 2^-105 relative to y.
+__device__ __forceinline__ dd qd_rsqrt_dd(const qd &s) {
+  const double y = 1.0 / sqrt(s.x0);
+  double t, te;
+  two_prod(y, y, t, te);
+  const dd u = dd_mul({s.x0, s.x1}, {t, te});
+  const double r = (1.0 - u.h) - u.l;
+  dd out;
+  fast_two_sum(y, 0.5 * (y * r), out.h, out.l);
+  return out;
+}
+// One Newton step of the inverse square root in qd, from the dd one: the
+// relative error goes from about 2^-103 to about 2^-206.
+__device__ __forceinline__ qd qd_rsqrt(const qd &s) {
+  const dd y1 = qd_rsqrt_dd(s);
+  const qd y = {y1.h, y1.l, 0.0, 0.0};
+  const qd r = qd_sub(qd_from(1.0), qd_mul(s, qd_mul(y, y)));
+  const qd h = qd_mul(y, r);
+  return qd_add(y, {0.5 * h.x0, 0.5 * h.x1, 0.5 * h.x2, 0.5 * h.x3});
+}
+// sqrt(s) for s > 0: the inverse square root y (qd_rsqrt), then x = s y
 // corrected once by y (s - x^2) / 2, which squares the error of y again.
 __device__ __forceinline__ qd qd_sqrt(qd s) {
-  qd y = qd_from(1.0 / sqrt(s.x0));
-  const qd one = qd_from(1.0);
-#pragma unroll 1
-  for (int it = 0; it < 2; ++it) {
-    qd r = qd_sub(one, qd_mul(s, qd_mul(y, y)));
-    qd h = qd_mul(y, r);
-    y = qd_add(y, {0.5 * h.x0, 0.5 * h.x1, 0.5 * h.x2, 0.5 * h.x3});
-  }
+  const qd y = qd_rsqrt(s);
   qd x = qd_mul(s, y);
   qd d = qd_sub(s, qd_mul(x, x));
   qd h = qd_mul(y, d);
@@ -220,19 +236,13 @@ __device__ __forceinline__ qd qd_sqrt(qd s) {
 }
 
 // sqrt(s) and 1/sqrt(s) together: the inverse square root y of qd_sqrt
-// (two Newton iterations from the FP64 one) is the reciprocal of the root
-// up to its last bits; one Newton step of the reciprocal from y,
-// y + y (1 - root y), takes it to full accuracy, in place of the three
-// iterations of qd_recip started from the FP64 reciprocal.
+// is the reciprocal of the root up to its last bits; one Newton step of the
+// reciprocal from y, y + y (1 - root y), takes it to full accuracy, in
+// place of the three iterations of qd_recip started from the FP64
+// reciprocal.
 __device__ __forceinline__ void qd_sqrt_recip(qd s, qd &root, qd &inv) {
-  qd y = qd_from(1.0 / sqrt(s.x0));
+  const qd y = qd_rsqrt(s);
   const qd one = qd_from(1.0);
-#pragma unroll 1
-  for (int it = 0; it < 2; ++it) {
-    qd r = qd_sub(one, qd_mul(s, qd_mul(y, y)));
-    qd h = qd_mul(y, r);
-    y = qd_add(y, {0.5 * h.x0, 0.5 * h.x1, 0.5 * h.x2, 0.5 * h.x3});
-  }
   qd x = qd_mul(s, y);
   qd d = qd_sub(s, qd_mul(x, x));
   qd h = qd_mul(y, d);
