@@ -425,7 +425,7 @@ def newton_context(torch, api, steps=None, paths=1024, path_steps=5):
 # schedule), counted by rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64
 # lanes, FMA = 2) over all step launches of one mgs_qr call
 # (profiles/mgs_step_qd_1024x1024.md).
-QD1024_FLOPS = 9.635e11
+QD1024_FLOPS = 9.632e11
 
 
 def qd_large(torch, api, n=1024, reps=2):
