@@ -28,13 +28,33 @@ __device__ __forceinline__ v4d mfma16x16x4(double a, double b, v4d c) {
 
 constexpr int NBP = 64;  // panel width of the blocked factorisation
 
+// The reduction index of a 16x16x4 product may follow any order of the
+// summed rows, as long as both operands use it.  The kernels below give
+// lane i + 16 kk the rows (or panel columns) 4 kk + s of a block of 16 in
+// product step s = 0..3: each lane then reads 4 consecutive entries of its
+// column at once, and the 4 lanes that share a column cover 128
+// contiguous bytes, one cache line per column instead of a quarter of one
+// per load.
+
+// Four consecutive doubles from p[0..3]; entries at or past `lim` (counted
+// from p) read as zero.  Whole blocks take wide loads.
+__device__ __forceinline__ void load4(const double *p, int lim, double (&v)[4]) {
+  if (lim >= 4) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = p[s];
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = s < lim ? p[s] : 0.0;
+  }
+}
+
 // W (NBP x N) = Q_p^H (NBP x m) A_t (m x N), complex, planar FP64.
 // Q_p: the panel's first column (plane stride plane), A_t: the first
 // trailing column, W: output with leading dimension ldw (R's block row).
 // One workgroup per 16 x 16 tile of W (grid: trailing column tiles x panel
 // column tiles, 4 x 124 = 496 workgroups for the first 2048 panel, enough
 // to occupy every compute unit); its QHA_SLICES waves each reduce over one
-// slice of the m rows (a multiple of 4), and the slice partials are then
+// slice of the m rows (a multiple of 16), and the slice partials are then
 // summed in slice order through LDS, so the result does not depend on
 // timing.
 constexpr int QHA_SLICES = 8;
@@ -49,22 +69,28 @@ __global__ __launch_bounds__(64 * QHA_SLICES) void zgemm_qha_kernel(int m, int N
   const int qc = i0 + li;  // panel column read by this lane (A operand)
   const int tc = j0 + li;  // trailing column read by this lane (B operand)
   const bool qok = qc < nbp, tok = tc < N;
-  const int mq = ((m + 4 * QHA_SLICES - 1) / (4 * QHA_SLICES)) * 4;  // rows per slice, multiple of 4
+  const int mq = ((m + 16 * QHA_SLICES - 1) / (16 * QHA_SLICES)) * 16;  // rows per slice, multiple of 16
   const int k0 = ks * mq, k1 = min(m, k0 + mq);
   v4d cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
   const double *qr = Qp + (size_t)(qok ? qc : 0) * ldq, *qi = qr + plane;
   const double *ar = At + (size_t)(tok ? tc : 0) * lda, *ai = ar + plane;
-#pragma unroll 4
-  for (int k = k0; k < k1; k += 4) {
-    const int row = k + lk;
-    const bool rok = row < k1;
-    const double a_r = (qok && rok) ? qr[row] : 0.0, a_i = (qok && rok) ? qi[row] : 0.0;
-    const double b_r = (tok && rok) ? ar[row] : 0.0, b_i = (tok && rok) ? ai[row] : 0.0;
-    // conj(q) a: re = qr ar + qi ai, im = qr ai - qi ar
-    cr = mfma16x16x4(a_r, b_r, cr);
-    cr = mfma16x16x4(a_i, b_i, cr);
-    ci = mfma16x16x4(a_r, b_i, ci);
-    ci = mfma16x16x4(-a_i, b_r, ci);
+#pragma unroll 2
+  for (int kb = k0; kb < k1; kb += 16) {
+    const int row = kb + 4 * lk;  // rows row .. row + 3 of this lane
+    const int lim = k1 - row;
+    double a_r[4], a_i[4], b_r[4], b_i[4];
+    load4(qr + row, qok ? lim : 0, a_r);
+    load4(qi + row, qok ? lim : 0, a_i);
+    load4(ar + row, tok ? lim : 0, b_r);
+    load4(ai + row, tok ? lim : 0, b_i);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      // conj(q) a: re = qr ar + qi ai, im = qr ai - qi ar
+      cr = mfma16x16x4(a_r[s], b_r[s], cr);
+      cr = mfma16x16x4(a_i[s], b_i[s], cr);
+      ci = mfma16x16x4(a_r[s], b_i[s], ci);
+      ci = mfma16x16x4(-a_i[s], b_r[s], ci);
+    }
   }
   if (ks > 0) {
 #pragma unroll
@@ -97,7 +123,9 @@ __global__ __launch_bounds__(64 * QHA_SLICES) void zgemm_qha_kernel(int m, int N
 }
 
 // A_t (m x N) -= Q_p (m x nbp) W (nbp x N).  One wave per 16 x 16 tile of
-// A_t, K = nbp in steps of 4.
+// A_t, K = nbp in blocks of 16 panel columns (the lane order above: W
+// read 4 consecutive rows at a time, Q_p one column per product step,
+// 16 consecutive rows across the lanes).
 __global__ __launch_bounds__(256) void zgemm_update_kernel(int m, int N, int nbp, const double *Qp, int ldq,
                                                             double *At, int lda, size_t plane, const double *W,
                                                             int ldw, size_t planeW) {
@@ -110,33 +138,40 @@ __global__ __launch_bounds__(256) void zgemm_update_kernel(int m, int N, int nbp
   const int li = lane & 15, lk = lane >> 4;
   // output tile values (D layout): row i0 + lk + 4r, column j0 + li
   const int oc = j0 + li;
+  const bool cok = oc < N;
   v4d cr, ci;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int orow = i0 + lk + 4 * r;
-    const bool ok = oc < N && orow < m;
+    const bool ok = cok && orow < m;
     cr[r] = ok ? At[(size_t)oc * lda + orow] : 0.0;
     ci[r] = ok ? At[(size_t)oc * lda + orow + plane] : 0.0;
   }
   const int arow = i0 + li;  // A operand row (Q_p)
   const bool aok = arow < m;
-  for (int k = 0; k < nbp; k += 4) {
-    const int kk = k + lk;
-    const bool kok = kk < nbp;
-    const double q_r = (aok && kok) ? Qp[(size_t)kk * ldq + arow] : 0.0;
-    const double q_i = (aok && kok) ? Qp[(size_t)kk * ldq + arow + plane] : 0.0;
-    const double w_r = (kok && oc < N) ? W[(size_t)oc * ldw + kk] : 0.0;
-    const double w_i = (kok && oc < N) ? W[(size_t)oc * ldw + kk + planeW] : 0.0;
-    // a -= q w: re -= qr wr - qi wi, im -= qr wi + qi wr
-    cr = mfma16x16x4(-q_r, w_r, cr);
-    cr = mfma16x16x4(q_i, w_i, cr);
-    ci = mfma16x16x4(-q_r, w_i, ci);
-    ci = mfma16x16x4(-q_i, w_r, ci);
+  const double *wr = W + (size_t)(cok ? oc : 0) * ldw, *wi = wr + planeW;
+  for (int kb = 0; kb < nbp; kb += 16) {
+    const int k = kb + 4 * lk;  // panel columns k .. k + 3 of this lane
+    const int lim = nbp - k;
+    double w_r[4], w_i[4];
+    load4(wr + k, cok ? lim : 0, w_r);
+    load4(wi + k, cok ? lim : 0, w_i);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const bool kok = aok && s < lim;
+      const double q_r = kok ? Qp[(size_t)(k + s) * ldq + arow] : 0.0;
+      const double q_i = kok ? Qp[(size_t)(k + s) * ldq + arow + plane] : 0.0;
+      // a -= q w: re -= qr wr - qi wi, im -= qr wi + qi wr
+      cr = mfma16x16x4(-q_r, w_r[s], cr);
+      cr = mfma16x16x4(q_i, w_i[s], cr);
+      ci = mfma16x16x4(-q_r, w_i[s], ci);
+      ci = mfma16x16x4(-q_i, w_r[s], ci);
+    }
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int orow = i0 + lk + 4 * r;
-    if (oc < N && orow < m) {
+    if (cok && orow < m) {
       At[(size_t)oc * lda + orow] = cr[r];
       At[(size_t)oc * lda + orow + plane] = ci[r];
     }
