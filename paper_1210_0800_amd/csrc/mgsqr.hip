@@ -439,18 +439,45 @@ int refine_solve(int m, int n, const double *A, int lda, const double *b, double
   if (rc != MGS_OK) return rc;
   hipLaunchKernelGGL((set_x_kernel<P>), dim3(ceil_div(n, 256)), dim3(256), 0, st, n, w.d64, x);
   const int nchunk = ceil_div(n, NBP);
+  // The correction's panel projections: one cooperative launch per step
+  // (proj_replay_kernel) when it can run, else two launches per panel.  The
+  // launches of a converged solve return at once, so the fixed max_iter
+  // steps cost little past convergence.
+  DevInfo d;
+  bool fused = m <= PR_MAX_ROWS && dev_info(d) && d.cus >= NBP;
+  const long long spin = fused ? (long long)d.wclk_khz * 2000 : 0;  // 2 s
+  const unsigned jitter = g_jitter.load(std::memory_order_relaxed);
   for (int it = 1; it <= max_iter; ++it) {
     hipLaunchKernelGGL((residual_partial_kernel<P::L>), dim3(ceil_div(m, 256), nchunk), dim3(256), 0, st, m, n, NBP,
                        A, lda, b, x, static_cast<PrecQD::Acc *>(w.partial), w.ctl);
     hipLaunchKernelGGL((residual_finish_kernel<PrecQD>), dim3(ceil_div(m, 256)), dim3(256), 0, st, m, nchunk,
                        static_cast<const PrecQD::Acc *>(w.partial), w.r64, w.ctl);
-    for (int k0 = 0; k0 < n; k0 += NBP) {
-      const int nb = n - k0 < NBP ? n - k0 : NBP;
-      const double *Qp = w.Q64 + (size_t)k0 * m;
-      hipLaunchKernelGGL(proj_w_kernel, dim3(nb), dim3(256), 0, st, m, Qp, m, planeQ, w.r64, w.y64 + k0, (size_t)n,
-                         w.ctl);
-      hipLaunchKernelGGL(proj_r_kernel, dim3(ceil_div(m, 256)), dim3(256), 0, st, m, nb, Qp, m, planeQ, w.y64 + k0,
-                         (size_t)n, w.r64, w.ctl);
+    if (fused) {
+      // arrivals at the grid barriers of the earlier steps (2 per panel, G each)
+      unsigned int base = (unsigned int)(it - 1) * 2u * (unsigned int)nchunk * (unsigned int)NBP;
+      const double *Qa = w.Q64;
+      size_t pq = planeQ, pw = (size_t)n;
+      double *ra = w.r64, *wa = w.y64;
+      RefineCtl *ctl = w.ctl;
+      int mm = m, nn = n;
+      long long sp = spin;
+      unsigned jt = jitter;
+      void *args[] = {&mm, &nn, &Qa, &pq, &ra, &wa, &pw, &ctl, &info, &base, &sp, &jt};
+      if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(proj_replay_kernel), dim3(NBP), dim3(256), args, 0,
+                                     st) != hipSuccess) {
+        (void)hipGetLastError();
+        fused = false;  // the barrier count is off from here: per-panel launches for the rest
+      }
+    }
+    if (!fused) {
+      for (int k0 = 0; k0 < n; k0 += NBP) {
+        const int nb = n - k0 < NBP ? n - k0 : NBP;
+        const double *Qp = w.Q64 + (size_t)k0 * m;
+        hipLaunchKernelGGL(proj_w_kernel, dim3(nb), dim3(256), 0, st, m, Qp, m, planeQ, w.r64, w.y64 + k0, (size_t)n,
+                           w.ctl);
+        hipLaunchKernelGGL(proj_r_kernel, dim3(ceil_div(m, 256)), dim3(256), 0, st, m, nb, Qp, m, planeQ, w.y64 + k0,
+                           (size_t)n, w.r64, w.ctl);
+      }
     }
     rc = backsolve_launch<PrecD>(n, w.R64, n, w.y64, w.d64, nullptr, st, planeR, skip);
     if (rc != MGS_OK) return rc;

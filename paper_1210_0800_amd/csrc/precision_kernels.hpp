@@ -14,6 +14,7 @@
 // x += d in dd / qd, until ||d|| <= tol ||x||, stagnation, or max_iter.
 #pragma once
 #include "mgs_kernels.hpp"
+#include "resident_kernels.hpp"
 
 namespace mgsq {
 
@@ -180,10 +181,12 @@ __global__ __launch_bounds__(256) void zgemm_update_kernel(int m, int N, int nbp
 
 // ------------------------------------------------------- refinement ------
 struct RefineCtl {
-  int status;  // 0 running, 1 converged, 2 stagnated, 3 factorisation failed
+  int status;  // 0 running, 1 converged, 2 stagnated, 3 factorisation failed or a grid wait timed out
   int iters;
   double dprev;
   double err_est;
+  unsigned int bar;    // arrivals at the grid barriers of proj_replay_kernel (zero at the start of a solve)
+  unsigned int abort;  // set when one of its waits timed out
 };
 
 // Columns of Q64 (m x (n+1), ld m) from the leading limbs of A and b.
@@ -197,6 +200,8 @@ __global__ __launch_bounds__(256) void copy_hi_kernel(int m, int n, const double
     ctl->iters = 0;
     ctl->dprev = INFINITY;
     ctl->err_est = INFINITY;
+    ctl->bar = 0u;
+    ctl->abort = 0u;
     *info = 0;
   }
   if (i >= m) return;
@@ -363,6 +368,132 @@ __global__ __launch_bounds__(256) void proj_r_kernel(int m, int nbp, const doubl
   }
   r[i] = xr;
   r[i + m] = xi;
+}
+
+// The correction's projections of all panels in one cooperative launch (one
+// per refinement step instead of two per panel): for each panel of NBP
+// columns, w_p = Q_p^H r (workgroup g forms columns g, g + G, ... with the
+// operations of proj_w_kernel), a grid barrier, r -= Q_p w_p (rows spread
+// over the grid, the operations of proj_r_kernel), a grid barrier.  Every
+// value is formed by one workgroup in a fixed order, so the results are
+// those of the per-panel kernels, bit for bit.  r and w pass between
+// workgroups with device-scope loads and stores (Q, written before the
+// launch, with plain loads), so a barrier needs no cache maintenance: every
+// wave waits for its stores to complete, then one thread per workgroup
+// counts its arrival in ctl->bar (which grows by G per barrier from `base`,
+// the arrivals of the earlier steps of this solve) and waits, bounded, for
+// the others; on a time-out the step ends with status 3 and
+// MGS_INFO_SYNC_TIMEOUT in info.  m <= PR_MAX_ROWS.
+constexpr int PR_MAX_ROWS = 4096;
+__global__ __launch_bounds__(256) void proj_replay_kernel(int m, int n, const double *Q, size_t planeQ, double *r,
+                                                           double *w, size_t planew, RefineCtl *ctl, int *info,
+                                                           unsigned int base, long long spin_ticks,
+                                                           unsigned jitter) {
+  if (ctl->status != 0) return;
+  constexpr int NS = PR_MAX_ROWS / 256;
+  __shared__ double sr[4], si[4];
+  __shared__ double wl[2][NBP];
+  __shared__ int ok;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int G = gridDim.x, g = blockIdx.x;
+  unsigned int target = base;
+  unsigned step = 0;
+  auto grid_barrier = [&]() __attribute__((always_inline)) -> bool {
+    res_jitter(jitter, step++);
+    wait_vmem();  // this wave's device-scope stores of r and w have completed
+    __syncthreads();
+    target += (unsigned int)G;
+    if (tid == 0) {
+      atomicAdd(&ctl->bar, 1u);
+      const long long t0 = wall_clock64();
+      int good = 1;
+      while (__hip_atomic_load(&ctl->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+            wall_clock64() - t0 > spin_ticks) {
+          __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          good = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      ok = good;
+    }
+    __syncthreads();
+    asm volatile("" ::: "memory");
+    return ok != 0;
+  };
+  auto fail = [&]() __attribute__((always_inline)) {
+    if (tid == 0) {
+      ctl->status = 3;
+      __hip_atomic_store(info, MGS_INFO_SYNC_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  };
+  for (int k0 = 0; k0 < n; k0 += NBP) {
+    const int nb = n - k0 < NBP ? n - k0 : NBP;
+    const double *Qp = Q + (size_t)k0 * m;
+    double *wp = w + k0;
+    if (g < nb) {
+      // this thread's rows tid + 256 s of r, all loads in flight together
+      double xr[NS], xi[NS];
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2) {
+        const int i = tid + 256 * s2;
+        xr[s2] = i < m ? coh_load(r + i) : 0.0;
+        xi[s2] = i < m ? coh_load(r + i + m) : 0.0;
+      }
+      for (int c = g; c < nb; c += G) {
+        const double *qr = Qp + (size_t)c * m, *qi = qr + planeQ;
+        double ar = 0.0, ai = 0.0;
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2) {
+          const int i = tid + 256 * s2;
+          if (i < m) {
+            ar = __fma_rn(qr[i], xr[s2], ar);
+            ar = __fma_rn(qi[i], xi[s2], ar);
+            ai = __fma_rn(qr[i], xi[s2], ai);
+            ai = __fma_rn(-qi[i], xr[s2], ai);
+          }
+        }
+#pragma unroll
+        for (int mask = 32; mask >= 1; mask >>= 1) {
+          ar += __shfl_xor(ar, mask);
+          ai += __shfl_xor(ai, mask);
+        }
+        if (lane == 0) {
+          sr[wave] = ar;
+          si[wave] = ai;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          coh_store(wp + c, ((sr[0] + sr[1]) + sr[2]) + sr[3]);
+          coh_store(wp + c + planew, ((si[0] + si[1]) + si[2]) + si[3]);
+        }
+        __syncthreads();
+      }
+    }
+    if (!grid_barrier()) return fail();
+    if (g * 256 < m) {
+      if (tid < nb) {
+        wl[0][tid] = coh_load(wp + tid);
+        wl[1][tid] = coh_load(wp + tid + planew);
+      }
+      __syncthreads();
+      for (int i = g * 256 + tid; i < m; i += G * 256) {
+        double xr = coh_load(r + i), xi = coh_load(r + i + m);
+        for (int c = 0; c < nb; ++c) {
+          const double qr = Qp[(size_t)c * m + i], qi = Qp[(size_t)c * m + i + planeQ];
+          const double wr = wl[0][c], wi = wl[1][c];
+          xr = __fma_rn(-qr, wr, xr);
+          xr = __fma_rn(qi, wi, xr);
+          xi = __fma_rn(-qr, wi, xi);
+          xi = __fma_rn(-qi, wr, xi);
+        }
+        coh_store(r + i, xr);
+        coh_store(r + i + m, xi);
+      }
+    }
+    if (!grid_barrier()) return fail();
+  }
 }
 
 // The FP64 solution as the dd / qd starting x (first solve).
