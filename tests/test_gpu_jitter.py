@@ -5,7 +5,9 @@ a pseudo-random pause (mgs_set_jitter).  A difference would be a race.
 Covered: the single-launch factorisation (dd 1024 x 1024 + b, FP64
 700 x 500 + b), the triangular solve across workgroups (n = 1024), the
 one-workgroup dd kernel (32 x 32), the batched kernel (64 systems), and the
-FP64 panels of the precision form's factorisation (mgs_qr64, 512 x 200).
+FP64 panels of the precision form's factorisation (mgs_qr64, 512 x 200),
+and the refinement's projections replayed in one cooperative launch per
+step (mgs_refine_solve, dd 600 x 300).
 """
 import numpy as np
 import pytest
@@ -79,3 +81,10 @@ def test_precision_form_panels_bitwise_under_jitter():
     A, b = T(p["A"][0]), T(p["b"][0])
     ref = under_jitter(lambda: api.mgs_qr64(A, b))
     assert int(ref["info"].item()) == 0
+
+
+def test_refinement_bitwise_under_jitter():
+    p = inputs.random_problem(2, 600, 300, seed=7, config=93)
+    A, b = T(p["A"]), T(p["b"])
+    ref = under_jitter(lambda: api.refine_lstsq(A, b, max_iter=12))
+    assert int(ref["info"].item()) == 0 and int(ref["iters"].item()) >= 1
