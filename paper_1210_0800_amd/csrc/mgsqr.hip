@@ -444,7 +444,9 @@ int refine_solve(int m, int n, const double *A, int lda, const double *b, double
   // launches of a converged solve return at once, so the fixed max_iter
   // steps cost little past convergence.
   DevInfo d;
-  bool fused = m <= PR_MAX_ROWS && dev_info(d) && d.cus >= NBP;
+  // (the barrier count of all steps must fit the 32-bit counter)
+  bool fused = m <= PR_MAX_ROWS && (long long)max_iter * 2 * nchunk * NBP < (1LL << 31) && dev_info(d) &&
+               d.cus >= NBP;
   const long long spin = fused ? (long long)d.wclk_khz * 2000 : 0;  // 2 s
   const unsigned jitter = g_jitter.load(std::memory_order_relaxed);
   for (int it = 1; it <= max_iter; ++it) {
