@@ -170,10 +170,12 @@ __device__ __forceinline__ void wave_reduce_re(typename P::Acc &acc) {
 }
 
 // Batched block reduction of the accumulators c in [c_lo, c_hi): wave
-// butterflies, then the NWAVE partials combined in wave order through LDS.
+// butterflies, then the partials of the first nwd waves combined in wave
+// order through LDS (the waves past them hold only rows beyond m, whose
+// partials are zero).
 template <class P, int BWM>
 __device__ __forceinline__ void block_reduce(typename P::Acc (&acc)[BWM], int c_lo, int c_hi,
-                                             typename P::Acc *lds, int wave, int lane) {
+                                             typename P::Acc *lds, int wave, int lane, int nwd) {
 #pragma unroll
   for (int c = 0; c < BWM; ++c)
     if (c >= c_lo && c < c_hi) wave_reduce<P>(acc[c]);
@@ -188,7 +190,8 @@ __device__ __forceinline__ void block_reduce(typename P::Acc (&acc)[BWM], int c_
     if (c >= c_lo && c < c_hi) {
       acc[c] = lds[c];
 #pragma unroll
-      for (int w = 1; w < NWAVE; ++w) P::acc_merge(acc[c], lds[w * BWM + c]);
+      for (int w = 1; w < NWAVE; ++w)
+        if (w < nwd) P::acc_merge(acc[c], lds[w * BWM + c]);
     }
   }
   lds_barrier();
@@ -205,6 +208,8 @@ __device__ __forceinline__ void panel_role(const StepArgs &a, typename P::Acc *l
   const int k0 = a.t * a.bw;
   const int nb = min(a.bw, a.n - k0);
   const bool first = a.t <= 1;
+  // waves holding rows below m (rows r WG + tid): the others' partials are zero
+  const int nwd = RP > 1 ? NWAVE : min(NWAVE, (a.m + 63) / 64);
   if (a.t == 0 && tid == 0 && a.init_info) *a.info = 0;
 
   C col[BWM][RP];
@@ -245,7 +250,7 @@ __device__ __forceinline__ void panel_role(const StepArgs &a, typename P::Acc *l
             for (int r = 0; r < RP; ++r) P::acc_cmulc(acc[c], q[r], col[c][r]);
           }
         }
-        block_reduce<P, BWM>(acc, 0, nb, lds, wave, lane);
+        block_reduce<P, BWM>(acc, 0, nb, lds, wave, lane, nwd);
 #pragma unroll
         for (int c = 0; c < BWM; ++c) {
           if (c < nb) {
@@ -273,7 +278,8 @@ __device__ __forceinline__ void panel_role(const StepArgs &a, typename P::Acc *l
       lds_barrier();
       Acc s = lds[c];
 #pragma unroll
-      for (int w = 1; w < NWAVE; ++w) P::acc_merge_re(s, lds[w * BWM + c]);
+      for (int w = 1; w < NWAVE; ++w)
+        if (w < nwd) P::acc_merge_re(s, lds[w * BWM + c]);
       lds_barrier();
       typename P::R s2 = P::acc_value_re(s);
       if (!P::ok_norm(s2) && tid == 0 && *a.info == 0) *a.info = a.kbase + k + 1;
@@ -306,7 +312,7 @@ __device__ __forceinline__ void panel_role(const StepArgs &a, typename P::Acc *l
         }
       }
       if (c + 1 < nb) {
-        block_reduce<P, BWM>(acc, c + 1, nb, lds, wave, lane);
+        block_reduce<P, BWM>(acc, c + 1, nb, lds, wave, lane, nwd);
 #pragma unroll
         for (int d = 0; d < BWM; ++d) {
           if (d > c && d < nb) {
@@ -337,6 +343,8 @@ __device__ __forceinline__ void trailing_role(const StepArgs &a, int blk, typena
   const int j = jstart + blk * TEAMS + team;
   const bool active = j < a.ncols;
   const bool first = a.t == 1;
+  // team waves holding rows below m (rows (r TW + tw_i) 64 + lane)
+  const int nwt = RPT > 1 ? TW : min(TW, (a.m + 63) / 64);
 
   C col[RPT];
   size_t ps = 0;
@@ -370,7 +378,8 @@ __device__ __forceinline__ void trailing_role(const StepArgs &a, int blk, typena
         lds_barrier();
         acc = lds[team * TW];
 #pragma unroll
-        for (int w = 1; w < TW; ++w) P::acc_merge(acc, lds[team * TW + w]);
+        for (int w = 1; w < TW; ++w)
+          if (w < nwt) P::acc_merge(acc, lds[team * TW + w]);
         lds_barrier();
       }
       if (active) {
@@ -406,7 +415,8 @@ __device__ __forceinline__ void trailing_role(const StepArgs &a, int blk, typena
       lds_barrier();
       acc = lds[team * TW];
 #pragma unroll
-      for (int w = 1; w < TW; ++w) P::acc_merge_re(acc, lds[team * TW + w]);
+      for (int w = 1; w < TW; ++w)
+        if (w < nwt) P::acc_merge_re(acc, lds[team * TW + w]);
       lds_barrier();
     }
     if (active && j == a.n && tw_i == 0 && lane == 0) {
