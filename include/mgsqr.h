@@ -219,6 +219,9 @@ int ls_adjoint(int m, int n, int prec, const double *A, int lda, const double *b
  *      ||d|| <= tol ||x||, or when ||d|| > ||d_prev|| / 2 (the corrections
  *      stalled; that d is not applied): converged to the attainable accuracy
  *      if the last applied ||d|| / ||x|| <= sqrt(tol), stagnation otherwise.
+ *      All of it is enqueued at once (no host synchronisation): the steps
+ *      after the stopping test return at once on the device, and the
+ *      projections of one step run in one cooperative launch.
  *   A [in] m x n planar (lda), b [in] m planar, x [out] n planar, all in
  *   `prec` limbs.  block must be 64 (MGS_ERR_PREC otherwise).  tol >= 0 (e.g. 2^-104 dd, 2^-209 qd).
  *   iters [out, device int or NULL]: refinement steps applied.
@@ -226,7 +229,8 @@ int ls_adjoint(int m, int n, int prec, const double *A, int lda, const double *b
  *   work: mgs_workspace_size(m, n, prec, MGS_OP_REFINE) bytes.
  *   info [device int]: 0 converged; k > 0 zero or non-finite norm at column
  *   k of the FP64 factorisation; -1 stagnated above sqrt(tol); -2 max_iter
- *   reached first.
+ *   reached first; MGS_INFO_SYNC_TIMEOUT when a bounded wait between
+ *   workgroups (the FP64 panels' single launch, the projections) ran out.
  * Convergence needs kappa(A) * 2^-53 well below 1 and a consistent or
  * nearly consistent system.
  */
