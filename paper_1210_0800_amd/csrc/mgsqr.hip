@@ -687,7 +687,8 @@ int small_launch_dd(const StepArgs &s, hipStream_t st) {
 // and several systems share a compute unit.
 template <class P, int NW, int CPW>
 int batched_launch(const BatArgs &a, hipStream_t st) {
-  static_assert(NW * CPW == BAT_MAX_COLS, "every column of [A b] needs a slot");
+  static_assert(NW * CPW <= BAT_MAX_COLS, "slots beyond the flags");
+  if (a.ncols > NW * CPW) return MGS_ERR_DIMS;  // every column of [A b] needs a slot
   const size_t shmem = sizeof(double) * 2 * P::L * (size_t)a.n * a.m;
   if (shmem > BAT_LDS_BYTES) return MGS_ERR_DIMS;
   if (a.batch == 0) return MGS_OK;
@@ -701,6 +702,10 @@ int batched_launch(const BatArgs &a, hipStream_t st) {
 int batched_dispatch(int prec, const BatArgs &a, hipStream_t st) {
   if (prec == 1) return batched_launch<PrecD, 4, 16>(a, st);
   if (prec == 2) return batched_launch<PrecDD, 8, 8>(a, st);
+  // qd: 16 waves of 4 slots cap a wave at 128 registers (four waves per
+  // SIMD), which spills; up to 36 columns, 12 waves of 3 slots (three
+  // waves per SIMD, 168 registers)
+  if (a.ncols <= 36) return batched_launch<PrecQD, 12, 3>(a, st);
   return batched_launch<PrecQD, 16, 4>(a, st);
 }
 bool batched_fits(int m, int n, int ncols, int prec) {
