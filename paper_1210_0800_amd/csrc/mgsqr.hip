@@ -702,11 +702,10 @@ int batched_launch(const BatArgs &a, hipStream_t st) {
 int batched_dispatch(int prec, const BatArgs &a, hipStream_t st) {
   if (prec == 1) {
     if (a.ncols <= 36) return batched_launch<PrecD, 12, 3>(a, st);
-    return batched_launch<PrecD, 4, 16>(a, st);
+    return batched_launch<PrecD, 16, 4>(a, st);
   }
   if (prec == 2) {
     if (a.ncols <= 36) return batched_launch<PrecDD, 12, 3>(a, st);
-    if (a.ncols <= 40) return batched_launch<PrecDD, 8, 5>(a, st);
     return batched_launch<PrecDD, 8, 8>(a, st);
   }
   // qd: 16 waves of 4 slots cap a wave at 128 registers (four waves per
