@@ -706,7 +706,7 @@ int batched_dispatch(int prec, const BatArgs &a, hipStream_t st) {
   }
   if (prec == 2) {
     if (a.ncols <= 36) return batched_launch<PrecDD, 12, 3>(a, st);
-    return batched_launch<PrecDD, 8, 8>(a, st);
+    return batched_launch<PrecDD, 16, 4>(a, st);
   }
   // qd: 16 waves of 4 slots cap a wave at 128 registers (four waves per
   // SIMD), which spills; up to 36 columns, 12 waves of 3 slots (three
